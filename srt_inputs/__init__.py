@@ -1,0 +1,9 @@
+"""Seeded synthetic inputs for the cylindrical-aperture spherical Radon transform.
+
+This package holds only input generators: sensor sample sets (angles, heights,
+radii), voxel grids and phantoms. It contains none of the transform's
+arithmetic, so that the HIP path and the FP64 oracle can both consume the same
+arrays without sharing any code that computes the method.
+"""
+from .configs import Aperture, cylinder_aperture, config, CONFIG_NAMES  # noqa: F401
+from . import phantoms  # noqa: F401

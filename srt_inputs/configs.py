@@ -1,0 +1,116 @@
+"""Voxel grids and cylindrical sensor apertures of the synthetic workloads.
+
+A cylindrical aperture is a set of sensor columns parallel to the z axis on a
+circle of radius R about the z axis (Sec. 2: sensors on one z-parallel line
+share the first circular transform). Column a sits at angle alpha_a; every
+column carries the same sensor heights z_h and the same sphere radii l_l
+(Alg. 1 inputs).
+
+Readings of what the paper leaves open (all stated once here):
+  * voxels are cell-centred on the cube [-W, W]^3 with M voxels per axis;
+  * alpha_a = 2*pi*a/N_a (uniform on [0, 2*pi));
+  * z_h = linspace(-W, W, N_h), end points included;
+  * l_l = l * l_max / N_l for l = 1..N_l (uniform on (0, l_max]);
+  * where a workload gives no l_max, l_max is the distance from a sensor to
+    the farthest voxel corner, sqrt((R + sqrt(2) W)^2 + (2W)^2).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass(frozen=True)
+class Aperture:
+    """A voxel grid plus a cylindrical aperture. Lengths share one unit."""
+
+    name: str
+    ms: int  # voxels along x and along y
+    mz: int  # voxels along z
+    x0: float  # lower corner of the grid in x and in y
+    z0: float  # lower corner of the grid in z
+    dxy: float  # voxel pitch in x and y
+    dz: float  # voxel pitch in z
+    radius: float  # cylinder radius R
+    angles: np.ndarray = field(repr=False)  # [N_a] radians
+    zpos: np.ndarray = field(repr=False)  # [N_h]
+    radii: np.ndarray = field(repr=False)  # [N_l], strictly increasing, > 0
+
+    @property
+    def n_angles(self) -> int:
+        return int(self.angles.size)
+
+    @property
+    def n_z(self) -> int:
+        return int(self.zpos.size)
+
+    @property
+    def n_radii(self) -> int:
+        return int(self.radii.size)
+
+    @property
+    def vol_shape(self):
+        return (self.mz, self.ms, self.ms)
+
+    @property
+    def data_shape(self):
+        return (self.n_angles, self.n_z, self.n_radii)
+
+    def summary(self) -> dict:
+        return {
+            "workload": self.name,
+            "grid": [self.ms, self.ms, self.mz],
+            "pitch": self.dxy,
+            "cyl_radius": self.radius,
+            "n_angles": self.n_angles,
+            "n_z": self.n_z,
+            "n_radii": self.n_radii,
+            "l_max": float(self.radii[-1]),
+        }
+
+
+def farthest_corner(radius: float, half_width: float) -> float:
+    """Distance from a sensor on the cylinder to the farthest grid corner."""
+    return float(np.hypot(radius + np.sqrt(2.0) * half_width, 2.0 * half_width))
+
+
+def cylinder_aperture(name: str, m: int, half_width: float, radius: float,
+                      n_angles: int, n_z: int, n_radii: int,
+                      l_max: float | None = None, mz: int | None = None) -> Aperture:
+    """Cubic grid [-W, W]^3 (M^3 voxels) with a uniform cylindrical aperture."""
+    mz = m if mz is None else mz
+    h = 2.0 * half_width / m
+    hz = 2.0 * half_width / mz
+    if l_max is None:
+        l_max = farthest_corner(radius, half_width)
+    angles = 2.0 * np.pi * np.arange(n_angles, dtype=np.float64) / n_angles
+    zpos = np.linspace(-half_width, half_width, n_z, dtype=np.float64)
+    radii = l_max * np.arange(1, n_radii + 1, dtype=np.float64) / n_radii
+    return Aperture(name=name, ms=m, mz=mz, x0=-half_width, z0=-half_width,
+                    dxy=h, dz=hz, radius=float(radius), angles=angles,
+                    zpos=zpos, radii=radii)
+
+
+CONFIG_NAMES = ("cfg1", "cfg2", "cfg3", "cfg5_64", "cfg5_128", "cfg5_192")
+
+
+def config(name: str) -> Aperture:
+    """The named workload geometries.
+
+    cfg1      32^3 on [-1,1]^3, R=1.5, 16 angles x 16 heights x 64 radii, l_max=3.5
+    cfg2      128^3 on [-1,1]^3, R=1.3, 128 x 128 x 512
+    cfg3      256^3 at 0.1 mm (W=12.8 mm), R=1.2 W, 512 x 256 x 1024 (PACT scale)
+    cfg5_N    N^3 on [-1,1]^3, R=1.3, N x N x 4N (serving mix, N in 64/128/192)
+    """
+    if name == "cfg1":
+        return cylinder_aperture("cfg1", 32, 1.0, 1.5, 16, 16, 64, l_max=3.5)
+    if name == "cfg2":
+        return cylinder_aperture("cfg2", 128, 1.0, 1.3, 128, 128, 512)
+    if name == "cfg3":
+        w = 12.8
+        return cylinder_aperture("cfg3", 256, w, 1.2 * w, 512, 256, 1024)
+    if name.startswith("cfg5_"):
+        n = int(name.split("_")[1])
+        return cylinder_aperture(name, n, 1.0, 1.3, n, n, 4 * n)
+    raise KeyError(name)
