@@ -1,0 +1,172 @@
+/*
+ * srt.h -- C ABI of the MI355X library for the discrete spherical Radon
+ * transform (SRT) on a cylindrical aperture.
+ *
+ * The SRT maps a volume f to its integrals over spheres of radius l centred
+ * at sensors r (surface measure; Sec. 2 of Lozenski et al., "An Efficient
+ * Implementation of the Spherical Radon Transform with Cylindrical
+ * Apertures"). For sensors arranged in columns parallel to z on a cylinder,
+ * Sec. 2 writes it as two circular Radon transforms (CRTs): a circle
+ * transform in every z-slice about the column centre, then a half-circle
+ * transform in the (z, rho) half-plane about each sensor height. Sec. 3.1
+ * discretises both on a piecewise-constant voxel basis as sparse matrices
+ * A12 (one per column) and A34 (shared by all columns); Alg. 1 is the
+ * forward, Alg. 2 the matched adjoint built from their transposes.
+ *
+ * Conventions shared by every entry point
+ *   - Volumes are [batch][mz][ms][ms] (z, y, x; x fastest).
+ *   - Sensor data are [batch][n_angles][n_z][n_radii] (radius fastest).
+ *   - Column a sits at (R cos angles[a], R sin angles[a]); the cylinder axis is
+ *     the z axis x = y = 0.
+ *   - Voxel (i, j, k) covers [x0 + i dxy, x0 + (i+1) dxy] x [x0 + j dxy, ...]
+ *     x [z0 + k dz, z0 + (k+1) dz].
+ *   - The rho axis of the intermediate image reuses the radii: cell l spans
+ *     the midpoints between neighbouring radii (outer edges half a spacing
+ *     beyond the end radii).
+ *   - Weights are exact arc lengths computed in FP64 on the device and
+ *     rounded once (round to nearest even) to the weight dtype.
+ *   - Every device pointer is owned by the caller; the plan owns its operator
+ *     storage. All apply calls are asynchronous and ordered on the given HIP
+ *     stream (NULL = the null stream).
+ *   - Every call returns a status and never aborts. On error the contents of
+ *     outputs are undefined and srt_last_error() (thread-local) says why.
+ */
+#ifndef SRT_H
+#define SRT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct srt_plan srt_plan; /* opaque; immutable after creation */
+
+typedef enum {
+  SRT_OK = 0,
+  SRT_EINVAL = 1,  /* bad argument: null pointer, size <= 0, non-finite value,
+                      radii not strictly increasing, dtype pair not supported,
+                      workspace too small, destroyed plan */
+  SRT_ENOMEM = 2,  /* device allocation failed or budget exceeded */
+  SRT_EDEVICE = 3, /* a HIP runtime call failed */
+  SRT_ENOTSUP = 4  /* valid request this build does not implement */
+} srt_status;
+
+typedef enum { SRT_F32 = 0, SRT_F64 = 1, SRT_BF16 = 2, SRT_F16 = 3 } srt_dtype;
+
+/* How the operators are held: STORED keeps CSR matrices and their
+ * transposes resident in HBM; ONTHEFLY is reserved (returns ENOTSUP);
+ * AUTO picks STORED. */
+typedef enum { SRT_OP_AUTO = 0, SRT_OP_STORED = 1, SRT_OP_ONTHEFLY = 2 } srt_opmode;
+
+typedef struct {
+  int32_t ms;  /* voxels along x and along y */
+  int32_t mz;  /* voxels along z */
+  double x0;   /* lower corner of the grid in x and in y */
+  double z0;   /* lower corner of the grid in z */
+  double dxy;  /* voxel pitch in x and y (> 0) */
+  double dz;   /* voxel pitch in z (> 0) */
+} srt_grid;
+
+/* Sizes of a plan's operators (for tests, footprints and FLOP counts). */
+typedef struct {
+  int64_t nnz_a12;        /* nonzeros of A12 stacked over columns (rows a*n_radii + l) */
+  int64_t nnz_a34;        /* nonzeros of A34 (rows h*n_radii + l, cols l'*mz + k) */
+  int32_t live_radii;     /* rho cells that any column's circles reach; A34
+                             columns with l' >= live_radii are dropped because
+                             the intermediate image is identically zero there */
+  int32_t n_angles, n_z, n_radii;
+  double weight_scale_a12; /* stored weight = arc length * scale (power of 2) */
+  double weight_scale_a34;
+} srt_plan_info;
+
+/*
+ * srt_plan_create -- build both CRT operators (Sec. 2, Sec. 3.1; Alg. 1
+ * inputs) for a grid and a cylindrical aperture.
+ *   grid        host pointer to the voxel grid
+ *   cyl_radius  R >= 0, radius of the sensor cylinder
+ *   angles      host, n_angles finite column angles (radians)
+ *   z_pos       host, n_z finite sensor heights
+ *   radii       host, n_radii sphere radii, > 0 and strictly increasing
+ *   value_dtype SRT_F32 or SRT_F64 (type of volumes and data)
+ *   weight_dtype SRT_F32/BF16/F16 with F32 values; SRT_F64 with F64 values
+ *   mode        SRT_OP_AUTO or SRT_OP_STORED
+ *   device      HIP device ordinal
+ *   hip_stream  stream the build runs on (the call returns after the build
+ *               has finished)
+ *   out         receives the plan; released with srt_plan_destroy
+ * Errors: EINVAL (arguments), ENOTSUP (ONTHEFLY, > 2^31 nonzeros), ENOMEM,
+ * EDEVICE.
+ */
+srt_status srt_plan_create(const srt_grid *grid, double cyl_radius,
+                           const double *angles, int32_t n_angles,
+                           const double *z_pos, int32_t n_z,
+                           const double *radii, int32_t n_radii,
+                           srt_dtype value_dtype, srt_dtype weight_dtype,
+                           srt_opmode mode, int32_t device, void *hip_stream,
+                           srt_plan **out);
+
+/*
+ * srt_forward -- Alg. 1 for every column and every batch item:
+ * data[b][a][h][l] = sum over (l', k) of A34[(h,l),(l',k)] *
+ *                    sum over p of A12_a[l', p] * vol[b][k][p].
+ *   vol        device, [batch][mz][ms][ms] of value_dtype (read only)
+ *   data       device, [batch][n_angles][n_z][n_radii] of value_dtype
+ *              (overwritten)
+ *   batch      >= 1
+ *   workspace  device scratch of at least the size srt_plan_footprint
+ *              reports, or NULL to use the plan's own (then calls on one plan
+ *              must not overlap)
+ *   workspace_bytes  size of workspace (ignored when workspace is NULL)
+ * Errors: EINVAL, ENOMEM (own workspace), EDEVICE.
+ */
+srt_status srt_forward(srt_plan *plan, const void *vol, void *data, int32_t batch,
+                       void *workspace, size_t workspace_bytes, void *hip_stream);
+
+/*
+ * srt_adjoint -- Alg. 2 summed over the columns of the aperture (the exact
+ * transpose of srt_forward): vol[b] = sum over a of A12_a^T A34^T data[b][a].
+ * Overwrites vol; arguments as in srt_forward with the roles of vol and data
+ * exchanged. The sum over columns runs in a fixed order (no atomics), so
+ * results are bitwise reproducible.
+ */
+srt_status srt_adjoint(srt_plan *plan, const void *data, void *vol, int32_t batch,
+                       void *workspace, size_t workspace_bytes, void *hip_stream);
+
+/* Releases the plan's device memory. NULL is accepted. Work queued on the
+ * plan must have completed (synchronise its streams first). */
+srt_status srt_plan_destroy(srt_plan *plan);
+
+/* Bytes the plan keeps resident and bytes of workspace one apply of
+ * `batch` items needs. Either output pointer may be NULL. */
+srt_status srt_plan_footprint(const srt_plan *plan, int32_t batch,
+                              size_t *resident_bytes, size_t *workspace_bytes);
+
+/* Operator sizes and storage scales. */
+srt_status srt_plan_get_info(const srt_plan *plan, srt_plan_info *info);
+
+/*
+ * srt_plan_export_coo -- copy one stored operator to host memory as COO
+ * triplets (row-major order) with weights converted back to arc lengths
+ * (stored value / scale, as double). For tests.
+ *   which     0 = A12 stacked (rows a*n_radii + l, cols j*ms + i),
+ *             1 = A34 (rows h*n_radii + l, cols l'*mz + k),
+ *             2 = stored transpose of A12 (rows = pixels),
+ *             3 = stored transpose of A34 (rows = cells (l', k))
+ *   capacity  length of rows/cols/vals; with capacity 0 the pointers may be
+ *             NULL and only *nnz is written
+ *   nnz       receives the number of stored entries
+ * Errors: EINVAL (capacity < nnz with non-zero capacity, bad `which`).
+ */
+srt_status srt_plan_export_coo(const srt_plan *plan, int32_t which, int64_t capacity,
+                               int64_t *nnz, int32_t *rows, int32_t *cols, double *vals);
+
+/* Thread-local description of the last error on the calling thread. */
+const char *srt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SRT_H */

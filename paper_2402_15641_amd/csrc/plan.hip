@@ -1,0 +1,284 @@
+// Plan lifetime, validation, footprints, export and error reporting.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "srt_internal.h"
+
+namespace srt {
+
+namespace {
+thread_local std::string g_last_error;
+
+// Makes `device` current for the scope and restores the caller's device.
+struct DeviceGuard {
+  int prev = -1;
+  hipError_t err = hipSuccess;
+  explicit DeviceGuard(int dev) {
+    err = hipGetDevice(&prev);
+    if (err == hipSuccess && prev != dev) err = hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+bool finite_all(const double *v, int32_t n) {
+  for (int32_t i = 0; i < n; ++i)
+    if (!std::isfinite(v[i])) return false;
+  return true;
+}
+
+Status validate_plan(const srt_plan *p) {
+  if (!p) return fail(SRT_EINVAL, "plan is NULL");
+  if (p->magic != kPlanMagic) return fail(SRT_EINVAL, "plan is not a live plan (destroyed?)");
+  return Status{};
+}
+
+srt_status finish(const Status &s) { return s.code; }
+
+void destroy_contents(srt_plan *p) {
+  p->a12.release();
+  p->a12t.release();
+  p->a34.release();
+  p->a34t.release();
+  (void)hipFree(p->d_geom);
+  (void)hipFree(p->own_ws);
+  p->d_geom = nullptr;
+  p->own_ws = nullptr;
+}
+
+Status create(const srt_grid *grid, double R, const double *angles, int32_t na,
+              const double *zpos, int32_t nh, const double *radii, int32_t nl,
+              srt_dtype vdt, srt_dtype wdt, srt_opmode mode, int32_t device, hipStream_t s,
+              srt_plan **out) {
+  if (!out) return fail(SRT_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!grid || !angles || !zpos || !radii) return fail(SRT_EINVAL, "NULL argument");
+  if (grid->ms <= 0 || grid->mz <= 0) return fail(SRT_EINVAL, "grid sizes must be positive");
+  if (!(std::isfinite(grid->x0) && std::isfinite(grid->z0) && std::isfinite(grid->dxy) &&
+        std::isfinite(grid->dz)) || grid->dxy <= 0 || grid->dz <= 0)
+    return fail(SRT_EINVAL, "grid origin and pitch must be finite, pitch > 0");
+  if (!std::isfinite(R) || R < 0) return fail(SRT_EINVAL, "cylinder radius must be finite and >= 0");
+  if (na <= 0 || nh <= 0 || nl <= 0) return fail(SRT_EINVAL, "sample counts must be positive");
+  if (!finite_all(angles, na) || !finite_all(zpos, nh) || !finite_all(radii, nl))
+    return fail(SRT_EINVAL, "sample positions must be finite");
+  if (radii[0] <= 0) return fail(SRT_EINVAL, "radii must be > 0");
+  for (int32_t i = 1; i < nl; ++i)
+    if (!(radii[i] > radii[i - 1])) return fail(SRT_EINVAL, "radii must be strictly increasing");
+  const bool pair_ok = (vdt == SRT_F32 && (wdt == SRT_F32 || wdt == SRT_BF16 || wdt == SRT_F16)) ||
+                       (vdt == SRT_F64 && wdt == SRT_F64);
+  if (!pair_ok) return fail(SRT_EINVAL, "unsupported (value, weight) dtype pair");
+  if (mode == SRT_OP_ONTHEFLY) return fail(SRT_ENOTSUP, "on-the-fly operators are not built");
+  if (mode != SRT_OP_AUTO && mode != SRT_OP_STORED) return fail(SRT_EINVAL, "unknown mode");
+  // Index ranges: every dense index below must fit in int32 rows/cols.
+  const int64_t npix = (int64_t)grid->ms * grid->ms;
+  if (npix > INT32_MAX || (int64_t)na * nl > INT32_MAX || (int64_t)nh * nl > INT32_MAX ||
+      (int64_t)nl * grid->mz > INT32_MAX || npix * grid->mz > ((int64_t)1 << 40))
+    return fail(SRT_ENOTSUP, "problem too large for 32-bit operator indices");
+  int ndev = 0;
+  SRT_HIP(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return fail(SRT_EINVAL, "device ordinal out of range");
+  DeviceGuard dg(device);
+  if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
+
+  srt_plan *p = new (std::nothrow) srt_plan();
+  if (!p) return fail(SRT_ENOMEM, "host allocation failed");
+  p->device = device;
+  p->vdtype = vdt;
+  p->wdtype = wdt;
+  auto bail = [&](Status st) {
+    destroy_contents(p);
+    delete p;
+    return st;
+  };
+  if (hipMalloc(&p->d_geom, sizeof(double) * ((size_t)na + nh + nl)) != hipSuccess)
+    return bail(fail(SRT_ENOMEM, "device allocation for geometry failed"));
+  std::vector<double> h((size_t)na + nh + nl);
+  std::memcpy(h.data(), angles, sizeof(double) * na);
+  std::memcpy(h.data() + na, zpos, sizeof(double) * nh);
+  std::memcpy(h.data() + na + nh, radii, sizeof(double) * nl);
+  hipError_t e = hipMemcpyAsync(p->d_geom, h.data(), sizeof(double) * h.size(),
+                                hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return bail(hip_fail(e, "upload of sample positions"));
+
+  Geometry &g = p->geo;
+  g.ms = grid->ms;
+  g.mz = grid->mz;
+  g.x0 = grid->x0;
+  g.z0 = grid->z0;
+  g.dxy = grid->dxy;
+  g.dz = grid->dz;
+  g.R = R;
+  g.na = na;
+  g.nh = nh;
+  g.nl = nl;
+  g.angles = p->d_geom;
+  g.zpos = p->d_geom + na;
+  g.radii = p->d_geom + na + nh;
+
+  Coo pieces;
+  auto free_pieces = [&]() {
+    (void)hipFree(pieces.keys);
+    (void)hipFree(pieces.vals);
+    pieces = Coo{};
+  };
+  Status st = a12_pieces(g, s, &pieces);
+  if (st.ok()) st = compact_a12(&pieces, nl, npix, s, &p->live);
+  if (st.ok())
+    st = build_csr_pair(&pieces, (int64_t)na * p->live, npix, wdt, s, &p->a12, &p->a12t);
+  free_pieces();
+  if (st.ok()) st = a34_pieces(g, p->live, s, &pieces);
+  if (st.ok())
+    st = build_csr_pair(&pieces, (int64_t)nh * nl, (int64_t)p->live * g.mz, wdt, s, &p->a34,
+                        &p->a34t);
+  free_pieces();
+  if (!st.ok()) return bail(st);
+  p->magic = kPlanMagic;
+  *out = p;
+  return Status{};
+}
+
+}  // namespace
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+Status fail(srt_status code, const std::string &msg) {
+  set_error(msg);
+  Status s;
+  s.code = code;
+  return s;
+}
+
+Status hip_fail(hipError_t e, const char *what) {
+  if (e == hipErrorOutOfMemory) {
+    (void)hipGetLastError();
+    return fail(SRT_ENOMEM, std::string(what) + ": out of device memory");
+  }
+  return fail(SRT_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+size_t dtype_size(srt_dtype t) {
+  switch (t) {
+    case SRT_F64: return 8;
+    case SRT_F32: return 4;
+    default: return 2;
+  }
+}
+
+}  // namespace srt
+
+using namespace srt;
+
+extern "C" {
+
+srt_status srt_plan_create(const srt_grid *grid, double cyl_radius, const double *angles,
+                           int32_t n_angles, const double *z_pos, int32_t n_z,
+                           const double *radii, int32_t n_radii, srt_dtype value_dtype,
+                           srt_dtype weight_dtype, srt_opmode mode, int32_t device,
+                           void *hip_stream, srt_plan **out) {
+  try {
+    return finish(create(grid, cyl_radius, angles, n_angles, z_pos, n_z, radii, n_radii,
+                         value_dtype, weight_dtype, mode, device, (hipStream_t)hip_stream, out));
+  } catch (...) {
+    return finish(fail(SRT_ENOMEM, "host exception during plan creation"));
+  }
+}
+
+srt_status srt_plan_destroy(srt_plan *plan) {
+  if (!plan) return SRT_OK;
+  if (plan->magic != kPlanMagic) return finish(fail(SRT_EINVAL, "plan is not a live plan"));
+  DeviceGuard dg(plan->device);
+  plan->magic = 0;
+  destroy_contents(plan);
+  delete plan;
+  return SRT_OK;
+}
+
+srt_status srt_plan_footprint(const srt_plan *plan, int32_t batch, size_t *resident,
+                              size_t *workspace) {
+  Status st = validate_plan(plan);
+  if (!st.ok()) return finish(st);
+  if (batch <= 0) return finish(fail(SRT_EINVAL, "batch must be >= 1"));
+  if (resident)
+    *resident = plan->a12.bytes() + plan->a12t.bytes() + plan->a34.bytes() + plan->a34t.bytes() +
+                sizeof(double) * ((size_t)plan->geo.na + plan->geo.nh + plan->geo.nl);
+  if (workspace) *workspace = workspace_bytes(plan, batch);
+  return SRT_OK;
+}
+
+srt_status srt_plan_get_info(const srt_plan *plan, srt_plan_info *info) {
+  Status st = validate_plan(plan);
+  if (!st.ok()) return finish(st);
+  if (!info) return finish(fail(SRT_EINVAL, "info is NULL"));
+  info->nnz_a12 = plan->a12.nnz;
+  info->nnz_a34 = plan->a34.nnz;
+  info->live_radii = plan->live;
+  info->n_angles = plan->geo.na;
+  info->n_z = plan->geo.nh;
+  info->n_radii = plan->geo.nl;
+  info->weight_scale_a12 = plan->a12.scale;
+  info->weight_scale_a34 = plan->a34.scale;
+  return SRT_OK;
+}
+
+srt_status srt_plan_export_coo(const srt_plan *plan, int32_t which, int64_t capacity,
+                               int64_t *nnz, int32_t *rows, int32_t *cols, double *vals) {
+  Status st = validate_plan(plan);
+  if (!st.ok()) return finish(st);
+  const Csr *m = which == 0 ? &plan->a12 : which == 1 ? &plan->a34 : which == 2 ? &plan->a12t
+                 : which == 3 ? &plan->a34t : nullptr;
+  if (!m) return finish(fail(SRT_EINVAL, "which must be 0..3"));
+  if (!nnz) return finish(fail(SRT_EINVAL, "nnz is NULL"));
+  *nnz = m->nnz;
+  if (capacity == 0) return SRT_OK;
+  if (capacity < m->nnz) return finish(fail(SRT_EINVAL, "capacity smaller than nnz"));
+  if (!rows || !cols || !vals) return finish(fail(SRT_EINVAL, "NULL output array"));
+  DeviceGuard dg(plan->device);
+  if (dg.err != hipSuccess) return finish(hip_fail(dg.err, "hipSetDevice"));
+  std::vector<int32_t> rp((size_t)m->nrows + 1);
+  const size_t wsz = dtype_size(m->wdtype);
+  std::vector<unsigned char> raw(wsz * (size_t)m->nnz);
+  hipError_t e = hipMemcpy(rp.data(), m->rowptr, sizeof(int32_t) * rp.size(), hipMemcpyDeviceToHost);
+  if (e == hipSuccess && m->nnz)
+    e = hipMemcpy(cols, m->cols, sizeof(int32_t) * m->nnz, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && m->nnz) e = hipMemcpy(raw.data(), m->vals, raw.size(), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return finish(hip_fail(e, "export copy"));
+  for (int64_t r = 0; r < m->nrows; ++r)
+    for (int32_t k = rp[r]; k < rp[r + 1]; ++k) rows[k] = (int32_t)r;
+  // A12 rows are stored as a * live + l; report them as a * n_radii + l.
+  const int64_t L = plan->live, NL = plan->geo.nl;
+  if (which == 0)
+    for (int64_t k = 0; k < m->nnz; ++k) rows[k] = (int32_t)((rows[k] / L) * NL + rows[k] % L);
+  if (which == 2)
+    for (int64_t k = 0; k < m->nnz; ++k) cols[k] = (int32_t)((cols[k] / L) * NL + cols[k] % L);
+  for (int64_t k = 0; k < m->nnz; ++k) {
+    double v;
+    const unsigned char *b = raw.data() + wsz * k;
+    if (m->wdtype == SRT_F64) {
+      std::memcpy(&v, b, 8);
+    } else if (m->wdtype == SRT_F32) {
+      float f;
+      std::memcpy(&f, b, 4);
+      v = f;
+    } else if (m->wdtype == SRT_BF16) {
+      uint32_t u = (uint32_t)(b[0] | (b[1] << 8)) << 16;
+      float f;
+      std::memcpy(&f, &u, 4);
+      v = f;
+    } else {
+      _Float16 hv;
+      std::memcpy(&hv, b, 2);
+      v = (double)(float)hv;
+    }
+    vals[k] = v / m->scale;
+  }
+  return SRT_OK;
+}
+
+const char *srt_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

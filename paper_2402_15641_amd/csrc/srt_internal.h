@@ -1,0 +1,99 @@
+// Internal declarations shared by the translation units of libsrt.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "srt.h"
+
+namespace srt {
+
+// Thread-local error text behind srt_last_error().
+void set_error(const std::string &msg);
+
+// A status plus message; `ok()` when status == SRT_OK.
+struct Status {
+  srt_status code = SRT_OK;
+  bool ok() const { return code == SRT_OK; }
+};
+
+Status fail(srt_status code, const std::string &msg);
+Status hip_fail(hipError_t e, const char *what);
+
+#define SRT_HIP(call)                                     \
+  do {                                                    \
+    hipError_t e_ = (call);                               \
+    if (e_ != hipSuccess) return ::srt::hip_fail(e_, #call); \
+  } while (0)
+
+#define SRT_TRY(expr)                 \
+  do {                                \
+    ::srt::Status s_ = (expr);        \
+    if (!s_.ok()) return s_;          \
+  } while (0)
+
+// One sparse operator in CSR form on the device. Column indices ascend in
+// every row; values are arc lengths times `scale`, stored in `wdtype`.
+struct Csr {
+  int64_t nrows = 0, ncols = 0, nnz = 0;
+  int32_t *rowptr = nullptr;  // nrows + 1
+  int32_t *cols = nullptr;    // nnz
+  void *vals = nullptr;       // nnz elements of wdtype
+  srt_dtype wdtype = SRT_F32;
+  double scale = 1.0;         // stored = arc length * scale (power of two)
+  size_t bytes() const;
+  void release();
+};
+
+// Geometry as the device sees it (device arrays owned by the plan).
+struct Geometry {
+  int32_t ms = 0, mz = 0;
+  double x0 = 0, z0 = 0, dxy = 0, dz = 0;
+  double R = 0;
+  int32_t na = 0, nh = 0, nl = 0;
+  const double *angles = nullptr;  // device [na]
+  const double *zpos = nullptr;    // device [nh]
+  const double *radii = nullptr;   // device [nl]
+};
+
+// Raw COO pieces of an operator: one entry per arc piece (duplicates allowed),
+// key = row * ncols + col.
+struct Coo {
+  int64_t n = 0;
+  uint64_t *keys = nullptr;
+  double *vals = nullptr;
+};
+
+// Geometry kernels (geometry.hip). `live` bounds the rho cells kept in A34.
+Status a12_pieces(const Geometry &g, hipStream_t s, Coo *out);
+Status a34_pieces(const Geometry &g, int32_t live, hipStream_t s, Coo *out);
+
+// Sparse build (sparse_build.hip): sort pieces by (row, col), merge duplicates,
+// form CSR of the operator and of its transpose, round weights.
+Status build_csr_pair(Coo *pieces, int64_t nrows, int64_t ncols, srt_dtype wdtype,
+                      hipStream_t s, Csr *op, Csr *op_t);
+// Finds L = 1 + the largest radius index any column's circle reaches (0 if
+// none) from the A12 pieces and renumbers their rows a * nl + l as a * L + l.
+Status compact_a12(Coo *pieces, int32_t nl, int64_t npix, hipStream_t s, int32_t *live);
+
+}  // namespace srt
+
+struct srt_plan {
+  uint32_t magic = 0;
+  int32_t device = 0;
+  srt_dtype vdtype = SRT_F32, wdtype = SRT_F32;
+  srt::Geometry geo;
+  double *d_geom = nullptr;  // angles | zpos | radii
+  int32_t live = 0;          // live rho cells
+  srt::Csr a12, a12t, a34, a34t;
+  void *own_ws = nullptr;
+  size_t own_ws_bytes = 0;
+};
+
+namespace srt {
+constexpr uint32_t kPlanMagic = 0x53525431u;  // "SRT1"
+size_t workspace_bytes(const srt_plan *p, int32_t batch);
+size_t dtype_size(srt_dtype t);
+}  // namespace srt

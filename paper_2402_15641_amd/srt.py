@@ -1,0 +1,119 @@
+"""Plan object over the C ABI: torch tensors in, torch tensors out.
+
+The plan holds both CRT operators (and their transposes) resident on the
+device. forward() is Alg. 1 over every sensor column, adjoint() is Alg. 2
+summed over columns. All arithmetic happens in libsrt; this file checks
+shapes and dtypes and allocates outputs.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import binding as B
+
+_TORCH = {"f32": torch.float32, "f64": torch.float64}
+
+
+class SRTPlan:
+    """Cylindrical-aperture SRT operator on one device.
+
+    Geometry: voxel (i, j, k) covers [x0 + i dxy, ...) x [x0 + j dxy, ...) x
+    [z0 + k dz, ...); sensor column a sits at (R cos angles[a], R sin angles[a])
+    with heights z_pos and sphere radii `radii` (strictly increasing).
+    Volumes are [B][mz][ms][ms]; data are [B][n_angles][n_z][n_radii].
+    """
+
+    def __init__(self, ms, mz, x0, z0, dxy, dz, cyl_radius, angles, z_pos, radii,
+                 value_dtype: str = "f32", weight_dtype: str | None = None,
+                 device=None, mode: str = "auto"):
+        if weight_dtype is None:
+            weight_dtype = value_dtype
+        dev = torch.device("cuda", torch.cuda.current_device()) if device is None \
+            else torch.device(device)
+        if dev.type != "cuda":
+            raise ValueError("SRTPlan needs a ROCm device")
+        self.device = dev
+        self.value_dtype, self.weight_dtype = value_dtype, weight_dtype
+        self.dtype = _TORCH[value_dtype]
+        self.ms, self.mz = int(ms), int(mz)
+        self.n_angles, self.n_z, self.n_radii = len(angles), len(z_pos), len(radii)
+        with torch.cuda.device(dev):
+            self.handle = B.srt_plan_create(ms, mz, x0, z0, dxy, dz, cyl_radius, angles, z_pos,
+                                            radii, value_dtype, weight_dtype, mode,
+                                            dev.index or 0)
+        self.info = B.srt_plan_get_info(self.handle)
+
+    @classmethod
+    def from_geometry(cls, g, **kw) -> "SRTPlan":
+        """From any object with ms, mz, x0, z0, dxy, dz, radius, angles, zpos, radii."""
+        return cls(g.ms, g.mz, g.x0, g.z0, g.dxy, g.dz, g.radius, g.angles, g.zpos, g.radii,
+                   **kw)
+
+    @property
+    def vol_shape(self):
+        return (self.mz, self.ms, self.ms)
+
+    @property
+    def data_shape(self):
+        return (self.n_angles, self.n_z, self.n_radii)
+
+    def _check(self, t: torch.Tensor, shape, name):
+        if t.device != self.device:
+            raise ValueError(f"{name} must be on {self.device}, got {t.device}")
+        if t.dtype != self.dtype:
+            raise ValueError(f"{name} must be {self.dtype}, got {t.dtype}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        if tuple(t.shape[-len(shape):]) != tuple(shape) or t.dim() not in (len(shape), len(shape) + 1):
+            raise ValueError(f"{name} must have shape [B,]{tuple(shape)}, got {tuple(t.shape)}")
+        return 1 if t.dim() == len(shape) else t.shape[0]
+
+    def forward(self, vol: torch.Tensor, out: torch.Tensor | None = None, workspace=None,
+                stream=None) -> torch.Tensor:
+        batch = self._check(vol, self.vol_shape, "vol")
+        shape = self.data_shape if vol.dim() == 3 else (batch,) + self.data_shape
+        if out is None:
+            out = torch.empty(shape, dtype=self.dtype, device=self.device)
+        else:
+            self._check(out, self.data_shape, "out")
+        if batch > 0:
+            B.srt_forward(self.handle, vol, out, batch, workspace, stream)
+        return out
+
+    def adjoint(self, data: torch.Tensor, out: torch.Tensor | None = None, workspace=None,
+                stream=None) -> torch.Tensor:
+        batch = self._check(data, self.data_shape, "data")
+        shape = self.vol_shape if data.dim() == 3 else (batch,) + self.vol_shape
+        if out is None:
+            out = torch.empty(shape, dtype=self.dtype, device=self.device)
+        else:
+            self._check(out, self.vol_shape, "out")
+        if batch > 0:
+            B.srt_adjoint(self.handle, data, out, batch, workspace, stream)
+        return out
+
+    def footprint(self, batch: int = 1):
+        return B.srt_plan_footprint(self.handle, batch)
+
+    def workspace(self, batch: int = 1) -> torch.Tensor:
+        """A caller-owned workspace tensor large enough for `batch` items."""
+        _, ws = self.footprint(batch)
+        return torch.empty(ws, dtype=torch.uint8, device=self.device)
+
+    def export_coo(self, which: int):
+        return B.srt_plan_export_coo(self.handle, which)
+
+    def flops(self, batch: int = 1) -> int:
+        """Multiply-adds of one forward (the adjoint does as many)."""
+        return batch * (self.info["nnz_a12"] * self.mz + self.info["nnz_a34"] * self.n_angles)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            B.srt_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

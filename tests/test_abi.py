@@ -1,0 +1,79 @@
+"""The C ABI library loads and exports every entry point include/srt.h
+declares; argument errors are reported before any device is touched (CPU)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2402_15641_amd import binding as B
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "srt.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(srt_[a-z_]+)\s*\(", text)))
+
+
+def test_header_and_binding_agree():
+    assert declared_functions() == sorted(B.SYMBOLS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = B.lib()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def _create(**over):
+    L = B.lib()
+    args = dict(grid=B.SrtGrid(8, 8, -1.0, -1.0, 0.25, 0.25), R=1.0,
+                angles=np.zeros(4), zpos=np.zeros(2), radii=np.array([0.5, 1.0]),
+                vdt=0, wdt=0, mode=0, device=0)
+    args.update(over)
+    out = ctypes.c_void_p(12345)
+    grid = args["grid"]
+    st = L.srt_plan_create(ctypes.byref(grid) if grid is not None else None, args["R"],
+                           args["angles"].ctypes.data, args["angles"].size,
+                           args["zpos"].ctypes.data, args["zpos"].size,
+                           args["radii"].ctypes.data, args["radii"].size,
+                           args["vdt"], args["wdt"], args["mode"], args["device"], None,
+                           ctypes.byref(out))
+    return st, out.value, B.srt_last_error()
+
+
+@pytest.mark.parametrize("over,needle", [
+    (dict(radii=np.array([1.0, 0.5])), "strictly increasing"),
+    (dict(radii=np.array([0.0, 0.5])), "> 0"),
+    (dict(angles=np.array([0.0, np.nan])), "finite"),
+    (dict(grid=B.SrtGrid(0, 8, -1.0, -1.0, 0.25, 0.25)), "positive"),
+    (dict(grid=B.SrtGrid(8, 8, -1.0, -1.0, -0.25, 0.25)), "pitch"),
+    (dict(R=float("inf")), "cylinder"),
+    (dict(vdt=1, wdt=0), "dtype"),
+    (dict(vdt=0, wdt=1), "dtype"),
+    (dict(grid=None), "NULL"),
+])
+def test_invalid_arguments_rejected(over, needle):
+    st, out, msg = _create(**over)
+    assert st == B.SRT_EINVAL
+    assert out is None
+    assert needle in msg
+
+
+def test_onthefly_mode_not_supported():
+    st, out, msg = _create(mode=2)
+    assert st == B.SRT_ENOTSUP
+
+
+def test_null_plan_calls():
+    L = B.lib()
+    assert L.srt_plan_destroy(None) == B.SRT_OK
+    assert L.srt_forward(None, None, None, 1, None, 0, None) == B.SRT_EINVAL
+    assert L.srt_adjoint(None, None, None, 1, None, 0, None) == B.SRT_EINVAL
+    r = ctypes.c_size_t()
+    assert L.srt_plan_footprint(None, 1, ctypes.byref(r), None) == B.SRT_EINVAL
+    n = ctypes.c_int64()
+    assert L.srt_plan_export_coo(None, 0, 0, ctypes.byref(n), None, None, None) == B.SRT_EINVAL

@@ -1,0 +1,227 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerances (relative L2 over a whole output unless stated):
+  FP64 values and weights   1e-12
+  FP32 values and weights   1e-5
+  BF16 / FP16 weights       5e-3
+  adjoint dot test (FP32)   1e-6 of ||A f|| ||g||
+  operator entries (FP64)   1e-12 * pitch per entry
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import geometry as geo, srt as osrt
+from srt_inputs import config, cylinder_aperture, phantoms
+from oracle_cache import operators, oracle_adjoint, oracle_forward, rel_l2, stacked
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm device")
+    from paper_2402_15641_amd import binding
+    binding.lib()
+
+
+def _plan(ap, value="f32", weight=None):
+    from paper_2402_15641_amd import SRTPlan
+    return SRTPlan.from_geometry(ap, value_dtype=value, weight_dtype=weight)
+
+
+def _t(x, dtype):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(device="cuda", dtype=dtype)
+
+
+def _np(t):
+    return t.detach().to("cpu", torch.float64).numpy()
+
+
+# ------------------------------------------------------------------ operators
+def test_operators_match_oracle_cfg1():
+    """Every stored weight equals the oracle's arc length (FP64 plan), the
+    transposes hold the same entries, and dropped rho cells are empty."""
+    ap, a12s, a34 = operators("cfg1")
+    plan = _plan(ap, "f64")
+    h = ap.dxy
+    r, c, v = plan.export_coo(0)
+    A = sp.csr_matrix((v, (r, c)), shape=(ap.n_angles * ap.n_radii, ap.ms ** 2))
+    assert abs(A - stacked(a12s)).max() <= 1e-12 * h
+    live = plan.info["live_radii"]
+    r, c, v = plan.export_coo(1)
+    B = sp.csr_matrix((v, (r, c)), shape=(ap.n_z * ap.n_radii, live * ap.mz))
+    assert abs(B - a34[:, :live * ap.mz]).max() <= 1e-12 * h
+    # rho cells at or beyond `live` receive no stage-1 value from any column
+    rows_l = np.concatenate([A.tocoo().row for A in a12s])
+    assert rows_l.size == 0 or rows_l.max() < live
+    # stored transposes are exact transposes
+    for which, M in ((2, A), (3, B)):
+        r, c, v = plan.export_coo(which)
+        T = sp.csr_matrix((v, (r, c)), shape=M.T.shape)
+        D = (T - M.T.tocsr())
+        assert D.nnz == 0 or abs(D).max() == 0.0
+
+
+@pytest.mark.parametrize("weight", ["bf16", "f16"])
+def test_rounded_weights_are_nearest(weight):
+    """16-bit weights are the FP64 arc lengths rounded once to nearest."""
+    ap, a12s, a34 = operators("cfg1")
+    plan = _plan(ap, "f32", weight)
+    r, c, v = plan.export_coo(1)
+    B = sp.csr_matrix((v, (r, c)), shape=(ap.n_z * ap.n_radii, plan.info["live_radii"] * ap.mz))
+    ref = a34[:, :B.shape[1]].tocsr()
+    scale = plan.info["weight_scale_a34"]
+    ulp = 2.0 ** -8 if weight == "bf16" else 2.0 ** -11  # half ulp bound, relative
+    diff = abs(B - ref).tocoo()
+    refv = np.asarray(ref[diff.row, diff.col]).ravel()
+    tiny = 2.0 ** (-133 if weight == "bf16" else -24) / scale
+    assert np.all(diff.data <= ulp * refv + tiny)
+
+
+# ------------------------------------------------------------------ cfg1
+@pytest.mark.parametrize("value,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_cfg1_forward_adjoint(value, tol):
+    ap, a12s, a34 = operators("cfg1")
+    F = phantoms.phantom(ap, 1)
+    g = phantoms.gaussian_data(ap, np.random.default_rng(2001))
+    dt = torch.float64 if value == "f64" else torch.float32
+    Ft, gt = _t(F, dt), _t(g, dt)
+    Fin, gin = _np(Ft), _np(gt)  # the exact values the device sees
+    plan = _plan(ap, value)
+    Y = plan.forward(Ft)
+    assert rel_l2(_np(Y), osrt.forward(Fin, a12s, a34, ap.n_z, ap.n_radii)) <= tol
+    Fp = plan.adjoint(gt)
+    assert rel_l2(_np(Fp), osrt.adjoint(gin, a12s, a34, ap.ms, ap.mz)) <= tol
+
+
+# ------------------------------------------------------------------ ragged / degenerate
+RAGGED = [
+    # ms, mz, R, na, nh, nl, batch: tails in every dimension, odd dense widths
+    (13, 7, 0.9, 5, 3, 11, 3),
+    (24, 65, 1.7, 7, 9, 70, 2),
+    (9, 3, 0.0, 4, 2, 6, 1),     # columns on the cylinder axis, inside the grid
+]
+
+
+@pytest.mark.parametrize("ms,mz,R,na,nh,nl,batch", RAGGED)
+@pytest.mark.parametrize("value", ["f64", "f32"])
+def test_ragged_shapes(ms, mz, R, na, nh, nl, batch, value):
+    ap = cylinder_aperture("ragged", ms, 1.0, R, na, nh, nl, mz=mz)
+    a12s, a34 = geo.assemble_all(ap)
+    rng = np.random.default_rng(ms * 1000 + mz)
+    vols = rng.uniform(-1, 1, (batch,) + ap.vol_shape)
+    data = rng.standard_normal((batch,) + ap.data_shape)
+    dt = torch.float64 if value == "f64" else torch.float32
+    tol = 1e-12 if value == "f64" else 1e-5
+    vt, dtt = _t(vols, dt), _t(data, dt)
+    plan = _plan(ap, value)
+    assert rel_l2(_np(plan.forward(vt)), oracle_forward(ap, a12s, a34, _np(vt))) <= tol
+    assert rel_l2(_np(plan.adjoint(dtt)), oracle_adjoint(ap, a12s, a34, _np(dtt))) <= tol
+
+
+def test_no_sphere_reaches_the_grid():
+    """Sensors far away with short radii: both transforms are exactly zero."""
+    ap = cylinder_aperture("far", 8, 1.0, 50.0, 4, 3, 5, l_max=2.0)
+    plan = _plan(ap, "f32")
+    assert plan.info["live_radii"] == 0 and plan.info["nnz_a12"] == 0
+    Y = plan.forward(torch.ones(ap.vol_shape, device="cuda"))
+    F = plan.adjoint(torch.ones(ap.data_shape, device="cuda"))
+    assert float(Y.abs().max()) == 0.0 and float(F.abs().max()) == 0.0
+
+
+def test_batch_and_workspace_are_bitwise_stable():
+    ap, a12s, a34 = operators("cfg1")
+    plan = _plan(ap, "f32")
+    rng = np.random.default_rng(9)
+    vols = _t(rng.uniform(0, 1, (3,) + ap.vol_shape), torch.float32)
+    Yb = plan.forward(vols)
+    for i in range(3):
+        assert torch.equal(plan.forward(vols[i].contiguous()), Yb[i])
+    ws = plan.workspace(3)
+    assert torch.equal(plan.forward(vols, workspace=ws), Yb)
+    Fb = plan.adjoint(Yb, workspace=ws)
+    assert torch.equal(plan.adjoint(Yb), Fb)
+    from paper_2402_15641_amd.binding import SRTError, SRT_EINVAL
+    with pytest.raises(SRTError) as e:
+        plan.forward(vols, workspace=ws[:1024])
+    assert e.value.status == SRT_EINVAL
+
+
+# ------------------------------------------------------------------ cfg2
+@pytest.fixture(scope="module")
+def cfg2():
+    ap, a12s, a34 = operators("cfg2")
+    F = phantoms.phantom(ap, 2)
+    Ft = _t(F, torch.float32)
+    Fin = _np(Ft)[None]
+    Y = oracle_forward(ap, a12s, a34, Fin)
+    g = phantoms.gaussian_data(ap, np.random.default_rng(2002))[None]
+    gt = _t(g, torch.float32)
+    Fp = oracle_adjoint(ap, a12s, a34, _np(gt))
+    return ap, Ft, gt, Y, Fp
+
+
+def test_cfg2_forward_adjoint_f32(cfg2):
+    ap, Ft, gt, Y, Fp = cfg2
+    plan = _plan(ap, "f32")
+    Yg = plan.forward(Ft[None].contiguous())
+    assert rel_l2(_np(Yg), Y) <= 1e-5
+    Fg = plan.adjoint(gt)
+    assert rel_l2(_np(Fg), Fp) <= 1e-5
+    # dot test on the device results, inner products in FP64
+    lhs = float((Yg.double() * gt.double()).sum())
+    rhs = float((Ft[None].double() * Fg.double()).sum())
+    assert abs(lhs - rhs) / (float(Yg.double().norm()) * float(gt.double().norm())) <= 1e-6
+
+
+@pytest.mark.parametrize("weight", ["bf16", "f16"])
+def test_cfg2_rounded_weights(cfg2, weight):
+    ap, Ft, gt, Y, Fp = cfg2
+    plan = _plan(ap, "f32", weight)
+    Yg = plan.forward(Ft[None].contiguous())
+    Fg = plan.adjoint(gt)
+    assert rel_l2(_np(Yg), Y) <= 5e-3
+    assert rel_l2(_np(Fg), Fp) <= 5e-3
+    lhs = float((Yg.double() * gt.double()).sum())
+    rhs = float((Ft[None].double() * Fg.double()).sum())
+    assert abs(lhs - rhs) / (float(Yg.double().norm()) * float(gt.double().norm())) <= 1e-6
+
+
+# ------------------------------------------------------------------ cfg3 (full size)
+def test_cfg3_sampled_forward_and_sparse_adjoint():
+    """At the 256^3 PACT-scale workload, in the launch configuration the
+    benchmark times: forward outputs of sampled (column, height) pairs against
+    the oracle, and the full adjoint volume of data that is non-zero on a few
+    columns and heights (the oracle needs only those rows)."""
+    ap = config("cfg3")
+    F = phantoms.phantom(ap, 3)
+    Ft = _t(F, torch.float32)
+    Fin = _np(Ft)
+    plan = _plan(ap, "f32")
+    Y = _np(plan.forward(Ft))
+    angles, heights = [0, 77, 300, 511], [0, 101, 255]
+    a34 = geo.assemble_a34(ap, heights=heights)
+    for a in angles:
+        G = osrt.stage1(geo.assemble_a12(ap, ap.angles[a]), Fin).reshape(-1)
+        for h in heights:
+            rows = a34[h * ap.n_radii:(h + 1) * ap.n_radii]
+            assert rel_l2(Y[a, h], rows @ G) <= 1e-5, (a, h)
+    rng = np.random.default_rng(2003)
+    data = np.zeros(ap.data_shape)
+    sel_a, sel_h = [5, 260], [10, 128]
+    for a in sel_a:
+        for h in sel_h:
+            data[a, h] = rng.standard_normal(ap.n_radii)
+    dt = _t(data, torch.float32)
+    Fp = _np(plan.adjoint(dt))
+    din = _np(dt)
+    a34s = geo.assemble_a34(ap, heights=sel_h)
+    ref = np.zeros(ap.vol_shape)
+    for a in sel_a:
+        Gp = osrt.adj_stage2(a34s, din[a], ap.n_radii, ap.mz)
+        ref += osrt.adj_stage1(geo.assemble_a12(ap, ap.angles[a]), Gp, ap.ms)
+    assert rel_l2(Fp, ref) <= 1e-5
