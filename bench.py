@@ -1,0 +1,231 @@
+#!/usr/bin/env python3
+"""Benchmark: spherical Radon transform forward+adjoint pairs per second.
+
+Workload (default): the PACT-scale cylindrical aperture -- 256^3 voxels at
+0.1 mm, cylinder radius 15.36 mm, 512 columns x 256 heights x 1024 radii,
+FP32 values, batch 1, phantom of 200 random thin cylinders (seeded). One step
+is one srt_forward followed by one srt_adjoint of its result, with the plan,
+the input volume and a caller workspace already resident in HBM.
+
+Prints one JSON line on stdout. Besides throughput it reports:
+  roofline      the dominant kernel's algorithmic FLOP rate, timed live with
+                HIP events recorded by the library on the apply stream, against
+                the FP32 vector-ALU peak (packed FP32 is disabled in this build);
+                `traffic` comes from the committed rocprofv3 counter summary
+                when it was taken on the current kernel source, else null
+  hbm           compulsory bytes of a pair (operators once, input, output)
+                over the pair time, against 8 TB/s
+  cpu_baseline  the FP64 oracle timed on the host on a bounded sample of the
+                same workload and scaled to one pair
+
+    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--weights f32|bf16|f16]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "SRT fwd+adjoint pairs/s at 256^3, HBM GB/s % of peak; serving p50/p99 latency"
+PEAK_FP32_VALU_TFLOPS = 78.6  # 256 CUs x 64 FMA lanes x 2 FLOP x 2.4 GHz (unpacked)
+PEAK_HBM_GBPS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stage_kernels_cfg3.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2402_15641_amd", "csrc", f)
+                  for f in ("apply.hip", "srt_internal.h")]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str, launches_per_pair: int):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    if it was taken on the current kernel source."""
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256") != kernel_source_hash():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    if not k:
+        return None
+    return k["fetch_bytes"] + k["write_bytes"]
+
+
+def cpu_baseline(ap, F64, n_cols=32, h_stride=8):
+    """The oracle (FP64, scipy CSR, one thread) on a bounded sample: Alg. 1
+    and Alg. 2 for n_cols evenly spaced columns, with the stage-2 operator
+    restricted to every h_stride-th sensor height; stage-1 time is scaled by
+    the columns left out, stage-2 time also by the heights left out."""
+    from oracle import geometry as geo, srt as osrt
+    cols = np.linspace(0, ap.n_angles, n_cols, endpoint=False).astype(int)
+    heights = list(range(0, ap.n_z, h_stride))
+    t0 = time.perf_counter()
+    a34 = geo.assemble_a34(ap, heights=heights)
+    a12s = [geo.assemble_a12(ap, ap.angles[a]) for a in cols]
+    t_asm = time.perf_counter() - t0
+    t1 = t2 = 0.0
+    for A in a12s:
+        s = time.perf_counter()
+        G = osrt.stage1(A, F64)
+        t1 += time.perf_counter() - s
+        s = time.perf_counter()
+        Y = osrt.stage2(a34, G, ap.n_z, ap.n_radii)
+        Gp = osrt.adj_stage2(a34, Y, ap.n_radii, ap.mz)
+        t2 += time.perf_counter() - s
+        s = time.perf_counter()
+        osrt.adj_stage1(A, Gp, ap.ms)
+        t1 += time.perf_counter() - s
+    scale = ap.n_angles / n_cols
+    t_pair = t1 * scale + t2 * scale * h_stride
+    return {"value": 1.0 / t_pair, "unit": "pairs/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n_cols} of {ap.n_angles} columns, stage 2 on {len(heights)} of "
+                      f"{ap.n_z} heights, forward+adjoint, scaled to one full pair "
+                      f"(sample apply {t1 + t2:.1f} s, assembly {t_asm:.1f} s not counted)",
+            "seconds_per_pair": t_pair}
+
+
+def main():
+    p = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--weights", default="f32", choices=["f32", "bf16", "f16"])
+    p.add_argument("--workload", default="cfg3", choices=["cfg3", "cfg2"])
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--profile-copy", action="store_true",
+                   help="also run one 1 GiB device copy (counter calibration)")
+    args = p.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU "
+              "angle-sharded path is design only", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from srt_inputs import config, phantoms
+    from paper_2402_15641_amd import SRTPlan, binding as B
+
+    if not torch.cuda.is_available():
+        log("bench.py needs a ROCm device")
+        sys.exit(1)
+    ap = config(args.workload)
+    cfg_num = 3 if args.workload == "cfg3" else 2
+    t0 = time.perf_counter()
+    F64 = phantoms.phantom(ap, cfg_num)
+    log(f"phantom {time.perf_counter() - t0:.1f} s")
+    vol = torch.from_numpy(F64).float().cuda()
+    F_in = vol.double().cpu().numpy()
+
+    t0 = time.perf_counter()
+    plan = SRTPlan.from_geometry(ap, value_dtype="f32", weight_dtype=args.weights)
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter() - t0
+    info = plan.info
+    log(f"plan {t_plan:.2f} s {info}")
+    ws = plan.workspace(1)
+    data = torch.empty(ap.data_shape, device="cuda")
+    back = torch.empty(ap.vol_shape, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    if args.profile_copy:
+        src = torch.ones(1 << 28, device="cuda")  # 1 GiB of FP32
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    for _ in range(args.warmup):
+        plan.forward(vol, out=data, workspace=ws)
+        plan.adjoint(data, out=back, workspace=ws)
+    torch.cuda.synchronize()
+
+    B.srt_plan_set_timing(plan.handle, True)
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for _ in range(args.steps):
+        plan.forward(vol, out=data, workspace=ws)
+        plan.adjoint(data, out=back, workspace=ws)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    ms_per_step = start.elapsed_time(stop) / args.steps
+    fwd_ms, n_f = B.srt_plan_stage_times(plan.handle, False)
+    adj_ms, n_a = B.srt_plan_stage_times(plan.handle, True)
+    B.srt_plan_set_timing(plan.handle, False)
+    fwd_ms = [t / n_f for t in fwd_ms]
+    adj_ms = [t / n_a for t in adj_ms]
+    log("stage ms fwd", [round(t, 3) for t in fwd_ms], "adj", [round(t, 3) for t in adj_ms])
+
+    # Algorithmic FLOPs per launch of each sparse stage (2 per multiply-add).
+    nnz12, nnz34 = info["nnz_a12"], info["nnz_a34"]
+    stages = {
+        "stage1_fwd": (fwd_ms[1], 2.0 * nnz12 * ap.mz),
+        "stage2_fwd": (fwd_ms[3], 2.0 * nnz34 * ap.n_angles),
+        "stage2_adj": (adj_ms[1], 2.0 * nnz34 * ap.n_angles),
+        "stage1_adj": (adj_ms[3], 2.0 * nnz12 * ap.mz),
+    }
+    dom = max(stages, key=lambda k: stages[k][0])
+    dom_ms, dom_flop = stages[dom]
+    achieved = dom_flop / (dom_ms * 1e-3) / 1e12
+    traffic = measured_traffic(dom, 1)
+
+    wb = {"f32": 4, "bf16": 2, "f16": 2}[args.weights]
+    op_bytes = 2 * (nnz12 + nnz34) * (4 + wb)  # operator and its transpose, once each
+    io_bytes = 2 * 4 * (int(np.prod(ap.vol_shape)) + int(np.prod(ap.data_shape)))
+    hbm_gbps = (op_bytes + io_bytes) / (ms_per_step * 1e-3) / 1e9
+
+    result = {
+        "metric": METRIC,
+        "value": 1000.0 / ms_per_step,
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.weights == "f32" else f"f32 (weights {args.weights})",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: " + ("256^3 voxels at 0.1 mm, R=15.36 mm, "
+                                                        "512 columns x 256 heights x 1024 radii"
+                                                        if args.workload == "cfg3" else
+                                                        "128^3 on [-1,1]^3, R=1.3, 128 x 128 x 512"),
+                   "batch": 1, "weights": args.weights, "phantom": "seeded",
+                   "nnz_a12": nnz12, "nnz_a34": nnz34, "plan_build_s": round(t_plan, 3)},
+        "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved,
+                     "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_VALU_TFLOPS, "traffic": traffic,
+                     "launch_ms": dom_ms, "flop_per_launch": dom_flop},
+        "hbm": {"compulsory_bytes_per_pair": op_bytes + io_bytes, "achieved_gbps": hbm_gbps,
+                "peak_gbps": PEAK_HBM_GBPS, "frac": hbm_gbps / PEAK_HBM_GBPS},
+        "stage_ms": {"forward": fwd_ms, "adjoint": adj_ms},
+    }
+    if not args.no_cpu_baseline:
+        t0 = time.perf_counter()
+        result["cpu_baseline"] = cpu_baseline(ap, F_in)
+        log(f"cpu baseline {time.perf_counter() - t0:.1f} s")
+    else:
+        result["cpu_baseline"] = None
+    plan.close()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

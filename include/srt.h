@@ -162,6 +162,25 @@ srt_status srt_plan_get_info(const srt_plan *plan, srt_plan_info *info);
 srt_status srt_plan_export_coo(const srt_plan *plan, int32_t which, int64_t capacity,
                                int64_t *nnz, int32_t *rows, int32_t *cols, double *vals);
 
+/*
+ * Stage timing (tracing). Each apply runs five stages in stream order:
+ *   forward: 0 volume layout, 1 stage 1 (A12), 2 intermediate layout,
+ *            3 stage 2 (A34), 4 data layout;
+ *   adjoint: 0 data layout, 1 stage 2 (A34^T), 2 intermediate layout,
+ *            3 stage 1 (sum over columns of A12^T), 4 volume layout.
+ * srt_plan_set_timing(plan, 1) clears earlier records and makes every later
+ * apply record HIP events between its stages on the apply's own stream;
+ * srt_plan_set_timing(plan, 0) stops and frees the records.
+ * srt_plan_stage_times sums the recorded durations (milliseconds) of the
+ * forward (adjoint = 0) or adjoint (adjoint = 1) applies into
+ * total_ms[0..n_stages) and reports how many applies were recorded. Call it
+ * only after synchronising the streams the applies ran on (EINVAL
+ * otherwise). Recording is not safe while another thread applies the plan.
+ */
+srt_status srt_plan_set_timing(srt_plan *plan, int32_t enable);
+srt_status srt_plan_stage_times(const srt_plan *plan, int32_t adjoint, int32_t n_stages,
+                                double *total_ms, int32_t *n_calls);
+
 /* Thread-local description of the last error on the calling thread. */
 const char *srt_last_error(void);
 

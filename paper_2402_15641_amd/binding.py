@@ -23,7 +23,8 @@ MODES = {"auto": 0, "stored": 1, "onthefly": 2}
 # Every entry point declared in include/srt.h.
 SYMBOLS = ("srt_plan_create", "srt_forward", "srt_adjoint", "srt_plan_destroy",
            "srt_plan_footprint", "srt_plan_get_info", "srt_plan_export_coo",
-           "srt_last_error")
+           "srt_plan_set_timing", "srt_plan_stage_times", "srt_last_error")
+STAGES = 5
 
 
 class SrtGrid(ctypes.Structure):
@@ -66,6 +67,9 @@ def lib() -> ctypes.CDLL:
     L.srt_plan_footprint.argtypes = [P, I32, ctypes.POINTER(SZ), ctypes.POINTER(SZ)]
     L.srt_plan_get_info.argtypes = [P, ctypes.POINTER(SrtPlanInfo)]
     L.srt_plan_export_coo.argtypes = [P, I32, I64, ctypes.POINTER(I64), P, P, P]
+    L.srt_plan_set_timing.argtypes = [P, I32]
+    L.srt_plan_stage_times.argtypes = [P, I32, I32, ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(I32)]
     for name in SYMBOLS[:-1]:
         getattr(L, name).restype = ctypes.c_int
     L.srt_last_error.argtypes = []
@@ -159,3 +163,16 @@ def srt_plan_export_coo(plan: int, which: int):
         _check(L.srt_plan_export_coo(plan, int(which), n, ctypes.byref(nnz), rows.ctypes.data,
                                      cols.ctypes.data, vals.ctypes.data), "srt_plan_export_coo")
     return rows, cols, vals
+
+
+def srt_plan_set_timing(plan: int, enable: bool) -> None:
+    _check(lib().srt_plan_set_timing(plan, 1 if enable else 0), "srt_plan_set_timing")
+
+
+def srt_plan_stage_times(plan: int, adjoint: bool):
+    """(summed milliseconds per stage, number of timed applies)."""
+    tot = (ctypes.c_double * STAGES)()
+    n = ctypes.c_int32()
+    _check(lib().srt_plan_stage_times(plan, 1 if adjoint else 0, STAGES, tot, ctypes.byref(n)),
+           "srt_plan_stage_times")
+    return list(tot), n.value

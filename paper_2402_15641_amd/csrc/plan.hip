@@ -40,10 +40,15 @@ Status validate_plan(const srt_plan *p) {
 srt_status finish(const Status &s) { return s.code; }
 
 void destroy_contents(srt_plan *p) {
+  clear_timing(p);
   p->a12.release();
   p->a12t.release();
   p->a34.release();
   p->a34t.release();
+  p->t12.release();
+  p->t12t.release();
+  p->t34.release();
+  p->t34t.release();
   (void)hipFree(p->d_geom);
   (void)hipFree(p->own_ws);
   p->d_geom = nullptr;
@@ -136,6 +141,14 @@ Status create(const srt_grid *grid, double R, const double *angles, int32_t na,
     st = build_csr_pair(&pieces, (int64_t)nh * nl, (int64_t)p->live * g.mz, wdt, s, &p->a34,
                         &p->a34t);
   free_pieces();
+  // Row-blocked copies for the applies: compact blocks of rows whose arcs
+  // share cells (8 columns x 32 radii, 16 heights x 16 radii, 16 x 16 rho-z
+  // cells, 16 x 16 pixels).
+  const int64_t L = p->live;
+  if (st.ok()) st = build_tiled(p->a12, RowGrid{na, L, 8, 32}, s, &p->t12);
+  if (st.ok()) st = build_tiled(p->a12t, RowGrid{grid->ms, grid->ms, 16, 16}, s, &p->t12t);
+  if (st.ok()) st = build_tiled(p->a34, RowGrid{nh, nl, 16, 16}, s, &p->t34);
+  if (st.ok()) st = build_tiled(p->a34t, RowGrid{L, grid->mz, 16, 16}, s, &p->t34t);
   if (!st.ok()) return bail(st);
   p->magic = kPlanMagic;
   *out = p;
@@ -159,6 +172,14 @@ Status hip_fail(hipError_t e, const char *what) {
     return fail(SRT_ENOMEM, std::string(what) + ": out of device memory");
   }
   return fail(SRT_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+void clear_timing(srt_plan *p) {
+  for (auto &list : p->timed) {
+    for (auto &rec : list)
+      for (auto &e : rec.ev) (void)hipEventDestroy(e);
+    list.clear();
+  }
 }
 
 size_t dtype_size(srt_dtype t) {
@@ -205,6 +226,7 @@ srt_status srt_plan_footprint(const srt_plan *plan, int32_t batch, size_t *resid
   if (batch <= 0) return finish(fail(SRT_EINVAL, "batch must be >= 1"));
   if (resident)
     *resident = plan->a12.bytes() + plan->a12t.bytes() + plan->a34.bytes() + plan->a34t.bytes() +
+                plan->t12.bytes() + plan->t12t.bytes() + plan->t34.bytes() + plan->t34t.bytes() +
                 sizeof(double) * ((size_t)plan->geo.na + plan->geo.nh + plan->geo.nl);
   if (workspace) *workspace = workspace_bytes(plan, batch);
   return SRT_OK;
@@ -276,6 +298,37 @@ srt_status srt_plan_export_coo(const srt_plan *plan, int32_t which, int64_t capa
     }
     vals[k] = v / m->scale;
   }
+  return SRT_OK;
+}
+
+srt_status srt_plan_set_timing(srt_plan *plan, int32_t enable) {
+  Status st = validate_plan(plan);
+  if (!st.ok()) return finish(st);
+  DeviceGuard dg(plan->device);
+  clear_timing(plan);
+  plan->timing = enable != 0;
+  return SRT_OK;
+}
+
+srt_status srt_plan_stage_times(const srt_plan *plan, int32_t adjoint, int32_t n_stages,
+                                double *total_ms, int32_t *n_calls) {
+  Status st = validate_plan(plan);
+  if (!st.ok()) return finish(st);
+  if (!total_ms || !n_calls || n_stages < 0 || n_stages > kStages)
+    return finish(fail(SRT_EINVAL, "bad output arguments"));
+  DeviceGuard dg(plan->device);
+  const auto &list = plan->timed[adjoint ? 1 : 0];
+  for (int32_t i = 0; i < n_stages; ++i) total_ms[i] = 0.0;
+  for (const auto &rec : list) {
+    for (int32_t i = 0; i < n_stages; ++i) {
+      float ms = 0.f;
+      hipError_t e = hipEventElapsedTime(&ms, rec.ev[i], rec.ev[i + 1]);
+      if (e == hipErrorNotReady) return finish(fail(SRT_EINVAL, "timed applies have not completed"));
+      if (e != hipSuccess) return finish(hip_fail(e, "hipEventElapsedTime"));
+      total_ms[i] += ms;
+    }
+  }
+  *n_calls = (int32_t)list.size();
   return SRT_OK;
 }
 

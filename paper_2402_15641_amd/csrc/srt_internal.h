@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "srt.h"
 
@@ -78,6 +79,46 @@ Status build_csr_pair(Coo *pieces, int64_t nrows, int64_t ncols, srt_dtype wdtyp
 // none) from the A12 pieces and renumbers their rows a * nl + l as a * L + l.
 Status compact_a12(Coo *pieces, int32_t nl, int64_t npix, hipStream_t s, int32_t *live);
 
+// ---- row-blocked operator format (tiled.hip)
+constexpr int kRB = 256;  // rows per block (one workgroup)
+constexpr int kC = 128;   // columns staged in LDS per chunk
+constexpr int kE = 1900;  // entries staged in LDS per chunk
+constexpr int kNW = 8;    // wavefronts per workgroup; each owns kRB / kNW rows
+
+// The operator's rows viewed as an n1 x n2 grid (row = i1 * n2 + i2), cut
+// into b1 x b2 blocks (b1 * b2 == kRB; edge blocks are partly empty).
+struct RowGrid {
+  int64_t n1 = 0, n2 = 0;
+  int64_t b1 = 0, b2 = 0;
+};
+
+struct Tiled {
+  int64_t nblk = 0, nchunk = 0, nnz = 0, ncols = 0;
+  int32_t *blk_rows = nullptr;     // [nblk * kRB], -1 where a block has no row
+  int32_t *blk_chunk = nullptr;    // [nblk + 1]
+  int32_t *chunk_cols = nullptr;   // [nchunk * kC]
+  int32_t *chunk_ncols = nullptr;  // [nchunk]
+  int32_t *chunk_ent = nullptr;    // [nchunk + 1] first entry of each chunk
+  int32_t *seg = nullptr;          // [nchunk * (kRB + 1)], offsets within the chunk
+  int32_t *ent_col = nullptr;      // [nnz] local column within the chunk
+  void *ent_w = nullptr;           // [nnz] weights in wdtype
+  srt_dtype wdtype = SRT_F32;
+  double scale = 1.0;
+  size_t bytes() const;
+  void release();
+};
+
+// Builds the row-blocked format of a CSR operator (weights copied as stored).
+Status build_tiled(const Csr &m, const RowGrid &g, hipStream_t s, Tiled *out);
+
+}  // namespace srt
+
+namespace srt {
+constexpr int kStages = 5;
+// HIP events of one timed apply: ev[i] .. ev[i+1] brackets stage i.
+struct StageEvents {
+  hipEvent_t ev[kStages + 1];
+};
 }  // namespace srt
 
 struct srt_plan {
@@ -87,13 +128,17 @@ struct srt_plan {
   srt::Geometry geo;
   double *d_geom = nullptr;  // angles | zpos | radii
   int32_t live = 0;          // live rho cells
-  srt::Csr a12, a12t, a34, a34t;
+  srt::Csr a12, a12t, a34, a34t;      // CSR operators (export and format source)
+  srt::Tiled t12, t12t, t34, t34t;    // row-blocked copies used by the applies
   void *own_ws = nullptr;
   size_t own_ws_bytes = 0;
+  bool timing = false;
+  std::vector<srt::StageEvents> timed[2];  // [0] forward, [1] adjoint
 };
 
 namespace srt {
 constexpr uint32_t kPlanMagic = 0x53525431u;  // "SRT1"
 size_t workspace_bytes(const srt_plan *p, int32_t batch);
 size_t dtype_size(srt_dtype t);
+void clear_timing(srt_plan *p);
 }  // namespace srt
