@@ -10,7 +10,8 @@ the input volume and a caller workspace already resident in HBM.
 Prints one JSON line on stdout. Besides throughput it reports:
   roofline      the dominant kernel's algorithmic FLOP rate, timed live with
                 HIP events recorded by the library on the apply stream, against
-                the FP32 vector-ALU peak (packed FP32 is disabled in this build);
+                the FP32 vector-ALU peak (157.3 TFLOP/s; gfx950 issues unpacked
+                v_fmac_f32 at that rate, packed FP32 is disabled in this build);
                 `traffic` comes from the committed rocprofv3 counter summary
                 when it was taken on the current kernel source, else null
   hbm           compulsory bytes of a pair (operators once, input, output)
@@ -35,7 +36,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "SRT fwd+adjoint pairs/s at 256^3, HBM GB/s % of peak; serving p50/p99 latency"
-PEAK_FP32_VALU_TFLOPS = 78.6  # 256 CUs x 64 FMA lanes x 2 FLOP x 2.4 GHz (unpacked)
+PEAK_FP32_VALU_TFLOPS = 157.3  # MI355X FP32 vector: 256 CUs x 128 FMA/clk x 2 FLOP x 2.4 GHz
 PEAK_HBM_GBPS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stage_kernels_cfg3.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2402_15641_amd", "csrc", f)

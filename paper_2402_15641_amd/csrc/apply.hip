@@ -42,145 +42,205 @@ template <typename T> struct LdsEnt {
   T w;
 };
 
-// Tile geometry shared by the kernel and its launcher.
+// Tile geometry shared by the kernel and its launcher. A wavefront is
+// GROUPS lane groups of LPG lanes; a group works on one row at a time and its
+// lanes split the dense slice: lane li holds NV vectors of VS values, vector m
+// at slice offset (m * LPG + li) * VS. One vector load of a group therefore
+// covers LPG * 16 = 256 contiguous bytes, i.e. every LDS bank once.
 template <typename T> struct TileShape {
   static constexpr int VS = 16 / sizeof(T);      // values per 16-byte vector
-  static constexpr int NV = 4;                   // vectors per lane
-  static constexpr int DW = 8 * NV * VS;         // dense values per slice (8 lanes per row)
+  static constexpr int LPG = 16;                 // lanes per group
+  static constexpr int GROUPS = 64 / LPG;        // groups per wavefront
+  static constexpr int NV = 2;                   // vectors per lane
+  static constexpr int DW = LPG * NV * VS;       // dense values per slice
   static constexpr int PIECES = DW / VS;         // 16-byte pieces per staged dense row
-  static constexpr int RPG = kRB / (kNW * 8);    // rows per lane group per wavefront
+  static_assert(kNW * GROUPS == kNQ, "one quad per lane group");
+  static constexpr int NT = kNW * 64;            // threads per workgroup
+  static constexpr int E = sizeof(T) == 4 ? kE32 : kE64;  // entries per chunk
+  static constexpr int DENSE_PER_T = kC * PIECES / NT;
+  static constexpr int ENT_PER_T = (E + NT - 1) / NT;
 };
 
-// One workgroup = one row block x one slice of the dense index; slices are
-// outermost in the grid so the current slice of the dense operand stays in
-// the last-level cache while every block streams through it.
+// One chunk's staged data while it travels from memory to LDS.
+template <typename T, typename WT> struct InFlight {
+  typename Vec16<T>::type dv[TileShape<T>::DENSE_PER_T];
+  int32_t ec[TileShape<T>::ENT_PER_T];
+  WT ew[TileShape<T>::ENT_PER_T];
+  int32_t sv;
+};
+
+// One workgroup (one per CU) = one row block x one slice of the dense
+// index; slices are outermost in the grid so the current slice of the dense
+// operand stays in the last-level cache while every block streams through it.
 //
-// Per chunk the whole workgroup stages the chunk's dense rows (DW values
-// each), its entries (converted to the accumulation type) and its per-row
-// entry offsets into LDS with one batch of coalesced loads. A wavefront is
-// 8 groups of 8 lanes: group q works on rows q, q+8, q+16, q+24 of the
-// wavefront's 32 rows, and each lane of a group owns NV vectors of the dense
-// slice (lane li holds values m*8*VS + li*VS .. +VS, m < NV, so a group reads
-// 8 consecutive 16-byte words per vector: conflict-free). Every entry is one
-// broadcast LDS read of (column, weight), one address computation and
-// NV*VS fused multiply-adds per lane.
-template <typename T, typename WT>
+// Chunks are double-buffered in LDS: while the wavefronts consume chunk c
+// from one buffer, the loads of chunk c+1 (its dense rows, entries and
+// per-row offsets) are in flight into registers and land in the other buffer
+// afterwards; the columns of chunk c+2 are fetched one step earlier still.
+// A wavefront is GROUPS lane groups (see TileShape); each group runs one
+// quad (kQ rows) in lockstep: per step it reads kQ entries (one per quad row,
+// padded so the rows advance together), kQ * NV dense vectors and does
+// kQ * NV * VS fused multiply-adds per lane.
+template <typename T, typename WT, bool VEC>
 __device__ __forceinline__ void tiled_body(const int32_t *__restrict__ blk_rows,
                                            const int32_t *__restrict__ blk_chunk,
                                            const int32_t *__restrict__ chunk_cols,
                                            const int32_t *__restrict__ chunk_ncols,
                                            const int32_t *__restrict__ chunk_ent,
-                                           const int32_t *__restrict__ seg,
+                                           const int32_t *__restrict__ qseg,
                                            const int32_t *__restrict__ ent_col,
                                            const WT *__restrict__ ent_w, const T *__restrict__ X,
                                            T *__restrict__ Y, int nblk, int D, T scale) {
   using S = TileShape<T>;
   using V16 = typename Vec16<T>::type;
-  constexpr int VS = S::VS, NV = S::NV, DW = S::DW, PIECES = S::PIECES, RPG = S::RPG;
-  constexpr int NT = kNW * 64;
-  constexpr int DENSE_PER_T = kC * PIECES / NT;
-  constexpr int ENT_PER_T = (kE + NT - 1) / NT;
-  __shared__ V16 lds_dense[kC * PIECES];
-  __shared__ LdsEnt<T> lds_ent[kE];
-  __shared__ int32_t lds_seg[kRB + 1];
+  constexpr int VS = S::VS, NV = S::NV, DW = S::DW, PIECES = S::PIECES;
+  constexpr int LPG = S::LPG, GROUPS = S::GROUPS;
+  constexpr int NT = S::NT, DPT = S::DENSE_PER_T, EPT = S::ENT_PER_T, E = S::E;
+  __shared__ V16 lds_dense[2][(kC + 1) * PIECES];  // column kC stays zero (padding)
+  __shared__ LdsEnt<T> lds_ent[2][E];
+  __shared__ int32_t lds_seg[2][kNQ + 1];
 
   const int bid = blockIdx.x;
   const int blk = bid % nblk, slice = bid / nblk;
   const int d0 = slice * DW;
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int lane = tid & 63, grp = lane >> 3, li = lane & 7;
+  const int lane = tid & 63, grp = lane / LPG, li = lane % LPG;
+  const int q = tid % PIECES;            // piece within a dense row
+  const int d_piece = d0 + q * VS;
+  // VEC: the dense width D is a multiple of VS, so rows are read and written
+  // in whole 16-byte vectors (otherwise element by element).
+  constexpr bool vec_ok = VEC;
 
-  V16 acc[RPG][NV];
+  V16 acc[kQ][NV];
 #pragma unroll
-  for (int j = 0; j < RPG; ++j)
+  for (int j = 0; j < kQ; ++j)
 #pragma unroll
     for (int m = 0; m < NV; ++m) acc[j][m] = V16{};
+  if (tid < PIECES) {
+    lds_dense[0][kC * PIECES + tid] = V16{};
+    lds_dense[1][kC * PIECES + tid] = V16{};
+  }
 
-  const bool vec_ok = (D % VS) == 0;
   const int c0 = blk_chunk[blk], c1 = blk_chunk[blk + 1];
-  for (int c = c0; c < c1; ++c) {
+
+  // Column of the dense row behind this thread's k-th piece of chunk c.
+  auto load_cols = [&](int c, int32_t *cols) {
+#pragma unroll
+    for (int k = 0; k < DPT; ++k) cols[k] = chunk_cols[(size_t)c * kC + (tid + k * NT) / PIECES];
+  };
+  auto issue = [&](int c, const int32_t *cols, InFlight<T, WT> &st) {
     const int n = chunk_ncols[c];
     const int ce0 = chunk_ent[c], ne = chunk_ent[c + 1] - ce0;
-    // ---- stage: every load of the chunk is issued before any LDS store
-    V16 dv[DENSE_PER_T];
-    int32_t ec[ENT_PER_T];
-    WT ew[ENT_PER_T];
-    int32_t sv = 0;
 #pragma unroll
-    for (int k = 0; k < DENSE_PER_T; ++k) {
-      const int i = tid + k * NT;
-      const int u = i / PIECES, q = i % PIECES;
-      const int d = d0 + q * VS;
-      dv[k] = V16{};
+    for (int k = 0; k < DPT; ++k) {
+      const int u = (tid + k * NT) / PIECES;
+      st.dv[k] = V16{};
       if (u < n) {
-        const T *src = X + (size_t)chunk_cols[(size_t)c * kC + u] * D + d;
-        if (vec_ok) {
-          if (d < D) dv[k] = *reinterpret_cast<const V16 *>(src);
+        const T *src = X + (size_t)cols[k] * D + d_piece;
+        if constexpr (VEC) {
+          if (d_piece < D) st.dv[k] = *reinterpret_cast<const V16 *>(src);
         } else {
-          T *dd = reinterpret_cast<T *>(&dv[k]);
+          T *dd = reinterpret_cast<T *>(&st.dv[k]);
 #pragma unroll
-          for (int v = 0; v < VS; ++v) dd[v] = d + v < D ? src[v] : T(0);
+          for (int v = 0; v < VS; ++v)
+            if (d_piece + v < D) dd[v] = src[v];
         }
       }
     }
 #pragma unroll
-    for (int k = 0; k < ENT_PER_T; ++k) {
+    for (int k = 0; k < EPT; ++k) {
       const int i = tid + k * NT;
+      st.ec[k] = 0;
+      st.ew[k] = WT{};
       if (i < ne) {
-        ec[k] = ent_col[ce0 + i];
-        ew[k] = ent_w[ce0 + i];
+        st.ec[k] = ent_col[ce0 + i];
+        st.ew[k] = ent_w[ce0 + i];
       }
     }
-    if (tid <= kRB) sv = seg[(size_t)c * (kRB + 1) + tid];
+    st.sv = tid <= kNQ ? qseg[(size_t)c * (kNQ + 1) + tid] : 0;
+  };
+  auto commit = [&](int buf, const InFlight<T, WT> &st) {
 #pragma unroll
-    for (int k = 0; k < DENSE_PER_T; ++k) lds_dense[tid + k * NT] = dv[k];
+    for (int k = 0; k < DPT; ++k) lds_dense[buf][tid + k * NT] = st.dv[k];
 #pragma unroll
-    for (int k = 0; k < ENT_PER_T; ++k) {
+    for (int k = 0; k < EPT; ++k) {
       const int i = tid + k * NT;
-      if (i < ne) lds_ent[i] = LdsEnt<T>{ec[k] * PIECES, to_acc<T, WT>(ew[k])};
+      if (i < E) lds_ent[buf][i] = LdsEnt<T>{st.ec[k] * PIECES, to_acc<T, WT>(st.ew[k])};
     }
-    if (tid <= kRB) lds_seg[tid] = sv;
+    if (tid <= kNQ) lds_seg[buf][tid] = st.sv;
+  };
+
+  if (c0 < c1) {
+    int32_t cols_next[DPT], cols_after[DPT];
+    InFlight<T, WT> st;
+    load_cols(c0, cols_next);
+    issue(c0, cols_next, st);
+    if (c0 + 1 < c1) load_cols(c0 + 1, cols_next);
+    commit(0, st);
     __syncthreads();
-    // ---- consume
+    for (int c = c0; c < c1; ++c) {
+      // Keep each chunk's loads inside its own iteration: if the compiler
+      // rotates some of them behind the barrier, the loop head waits for them.
+      asm volatile("" ::: "memory");
+      const int cur = (c - c0) & 1;
+      const bool more = c + 1 < c1;
+      if (more) {
+        issue(c + 1, cols_next, st);
+        if (c + 2 < c1) load_cols(c + 2, cols_after);
+      }
+      // ---- consume chunk c: this lane group's quad, kQ rows in lockstep
+      {
+        const int q = wave * GROUPS + grp;
+        const int e0 = lds_seg[cur][q], e1 = lds_seg[cur][q + 1];
+        for (int e = e0; e < e1; e += kQ) {
+          LdsEnt<T> en[kQ];
 #pragma unroll
-    for (int j = 0; j < RPG; ++j) {
-      const int pos = wave * (8 * RPG) + j * 8 + grp;
-      const int e0 = lds_seg[pos], e1 = lds_seg[pos + 1];
-#pragma unroll 2
-      for (int e = e0; e < e1; ++e) {
-        const LdsEnt<T> en = lds_ent[e];
-        const V16 *g = lds_dense + en.col + li;
+          for (int j = 0; j < kQ; ++j) en[j] = lds_ent[cur][e + j];
+          V16 x[kQ][NV];
 #pragma unroll
-        for (int m = 0; m < NV; ++m) {
-          const V16 x = g[m * 8];
-          const T *xs = reinterpret_cast<const T *>(&x);
-          T *as = reinterpret_cast<T *>(&acc[j][m]);
+          for (int j = 0; j < kQ; ++j)
 #pragma unroll
-          for (int v = 0; v < VS; ++v) as[v] = fma(en.w, xs[v], as[v]);
+            for (int m = 0; m < NV; ++m) x[j][m] = lds_dense[cur][en[j].col + li + m * LPG];
+#pragma unroll
+          for (int j = 0; j < kQ; ++j)
+#pragma unroll
+            for (int m = 0; m < NV; ++m) {
+              const T *xs = reinterpret_cast<const T *>(&x[j][m]);
+              T *as = reinterpret_cast<T *>(&acc[j][m]);
+#pragma unroll
+              for (int v = 0; v < VS; ++v) as[v] = fma(en[j].w, xs[v], as[v]);
+            }
         }
       }
+      if (more) {
+        commit(cur ^ 1, st);
+#pragma unroll
+        for (int k = 0; k < DPT; ++k) cols_next[k] = cols_after[k];
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
   // ---- write: each row once
 #pragma unroll
-  for (int j = 0; j < RPG; ++j) {
-    const int pos = wave * (8 * RPG) + j * 8 + grp;
-    const int row = blk_rows[(size_t)blk * kRB + pos];
+  for (int j = 0; j < kQ; ++j) {
+    const int slot = (wave * GROUPS + grp) * kQ + j;
+    const int row = blk_rows[(size_t)blk * kRB + slot];
     if (row < 0) continue;
 #pragma unroll
     for (int m = 0; m < NV; ++m) {
-      const int d = d0 + m * 8 * VS + li * VS;
+      const int d = d0 + (m * LPG + li) * VS;
       T *y = Y + (size_t)row * D + d;
       const T *as = reinterpret_cast<const T *>(&acc[j][m]);
-      if (vec_ok && d < D) {
-        V16 o;
-        T *os = reinterpret_cast<T *>(&o);
+      if constexpr (VEC) {
+        if (d < D) {
+          V16 o;
+          T *os = reinterpret_cast<T *>(&o);
 #pragma unroll
-        for (int v = 0; v < VS; ++v) os[v] = as[v] * scale;
-        *reinterpret_cast<V16 *>(y) = o;
-      } else if (!vec_ok) {
+          for (int v = 0; v < VS; ++v) os[v] = as[v] * scale;
+          *reinterpret_cast<V16 *>(y) = o;
+        }
+      } else {
 #pragma unroll
         for (int v = 0; v < VS; ++v)
           if (d + v < D) y[v] = as[v] * scale;
@@ -191,15 +251,15 @@ __device__ __forceinline__ void tiled_body(const int32_t *__restrict__ blk_rows,
 
 // One named kernel per stage so traces tell the stages apart.
 #define SRT_STAGE_KERNEL(NAME)                                                                 \
-  template <typename T, typename WT>                                                           \
-  __global__ __launch_bounds__(kNW * 64) __attribute__((amdgpu_waves_per_eu(4, 4))) void NAME( \
+  template <typename T, typename WT, bool VEC>                                                 \
+  __global__ __launch_bounds__(kNW * 64) void NAME(                                           \
       const int32_t *__restrict__ blk_rows, const int32_t *__restrict__ blk_chunk,             \
       const int32_t *__restrict__ chunk_cols, const int32_t *__restrict__ chunk_ncols,         \
-      const int32_t *__restrict__ chunk_ent, const int32_t *__restrict__ seg,                  \
+      const int32_t *__restrict__ chunk_ent, const int32_t *__restrict__ qseg,                 \
       const int32_t *__restrict__ ent_col, const WT *__restrict__ ent_w,                       \
       const T *__restrict__ X, T *__restrict__ Y, int nblk, int D, T scale) {                  \
-    tiled_body<T, WT>(blk_rows, blk_chunk, chunk_cols, chunk_ncols, chunk_ent, seg, ent_col,   \
-                      ent_w, X, Y, nblk, D, scale);                                            \
+    tiled_body<T, WT, VEC>(blk_rows, blk_chunk, chunk_cols, chunk_ncols, chunk_ent, qseg,      \
+                           ent_col, ent_w, X, Y, nblk, D, scale);                              \
   }
 SRT_STAGE_KERNEL(stage1_fwd)  // A12_a applied to every slice: G = A12 F
 SRT_STAGE_KERNEL(stage2_fwd)  // A34 applied to every column: Y = A34 G
@@ -267,14 +327,15 @@ Status spmm(Stage st, const Tiled &m, const T *X, T *Y, int D, hipStream_t s) {
   const WT *w = (const WT *)m.ent_w;
   auto go = [&](auto kern) {
     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kNW * 64), 0, s, m.blk_rows, m.blk_chunk,
-                       m.chunk_cols, m.chunk_ncols, m.chunk_ent, m.seg, m.ent_col, w, X, Y,
+                       m.chunk_cols, m.chunk_ncols, m.chunk_ent, m.qseg, m.ent_col, w, X, Y,
                        (int)m.nblk, D, scale);
   };
+  const bool vec = D % TileShape<T>::VS == 0;
   switch (st) {
-    case Stage::s1_fwd: go(stage1_fwd<T, WT>); break;
-    case Stage::s2_fwd: go(stage2_fwd<T, WT>); break;
-    case Stage::s2_adj: go(stage2_adj<T, WT>); break;
-    case Stage::s1_adj: go(stage1_adj<T, WT>); break;
+    case Stage::s1_fwd: vec ? go(stage1_fwd<T, WT, true>) : go(stage1_fwd<T, WT, false>); break;
+    case Stage::s2_fwd: vec ? go(stage2_fwd<T, WT, true>) : go(stage2_fwd<T, WT, false>); break;
+    case Stage::s2_adj: vec ? go(stage2_adj<T, WT, true>) : go(stage2_adj<T, WT, false>); break;
+    case Stage::s1_adj: vec ? go(stage1_adj<T, WT, true>) : go(stage1_adj<T, WT, false>); break;
   }
   SRT_HIP(hipGetLastError());
   return Status{};

@@ -143,12 +143,15 @@ Status create(const srt_grid *grid, double R, const double *angles, int32_t na,
   free_pieces();
   // Row-blocked copies for the applies: compact blocks of rows whose arcs
   // share cells (8 columns x 32 radii, 16 heights x 16 radii, 16 x 16 rho-z
-  // cells, 16 x 16 pixels).
+  // cells, 16 x 16 pixels). Rows processed side by side get equal work per
+  // chunk: one radius at 8 columns (A12), one radius at 8 heights (A34), 8
+  // z-neighbouring cells (A34^T), 8 x-neighbouring pixels (A12^T).
   const int64_t L = p->live;
-  if (st.ok()) st = build_tiled(p->a12, RowGrid{na, L, 8, 32}, s, &p->t12);
-  if (st.ok()) st = build_tiled(p->a12t, RowGrid{grid->ms, grid->ms, 16, 16}, s, &p->t12t);
-  if (st.ok()) st = build_tiled(p->a34, RowGrid{nh, nl, 16, 16}, s, &p->t34);
-  if (st.ok()) st = build_tiled(p->a34t, RowGrid{L, grid->mz, 16, 16}, s, &p->t34t);
+  const int me = vdt == SRT_F64 ? kE64 : kE32;
+  if (st.ok()) st = build_tiled(p->a12, RowGrid{na, L, 8, 32, true}, me, s, &p->t12);
+  if (st.ok()) st = build_tiled(p->a12t, RowGrid{grid->ms, grid->ms, 16, 16, false}, me, s, &p->t12t);
+  if (st.ok()) st = build_tiled(p->a34, RowGrid{nh, nl, 16, 16, true}, me, s, &p->t34);
+  if (st.ok()) st = build_tiled(p->a34t, RowGrid{L, grid->mz, 16, 16, false}, me, s, &p->t34t);
   if (!st.ok()) return bail(st);
   p->magic = kPlanMagic;
   *out = p;

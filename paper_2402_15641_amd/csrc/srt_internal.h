@@ -80,36 +80,45 @@ Status build_csr_pair(Coo *pieces, int64_t nrows, int64_t ncols, srt_dtype wdtyp
 Status compact_a12(Coo *pieces, int32_t nl, int64_t npix, hipStream_t s, int32_t *live);
 
 // ---- row-blocked operator format (tiled.hip)
-constexpr int kRB = 256;  // rows per block (one workgroup)
-constexpr int kC = 128;   // columns staged in LDS per chunk
-constexpr int kE = 1900;  // entries staged in LDS per chunk
-constexpr int kNW = 8;    // wavefronts per workgroup; each owns kRB / kNW rows
+constexpr int kRB = 256;   // rows per block (one workgroup)
+constexpr int kQ = 4;      // rows per quad: a lane group runs a quad in lockstep
+constexpr int kNQ = kRB / kQ;  // quads per block
+constexpr int kC = 128;    // columns staged in LDS per chunk
+constexpr int kE32 = 1920; // padded entries staged in LDS per chunk (FP32 values)
+constexpr int kE64 = 960;  // padded entries staged in LDS per chunk (FP64 values)
+constexpr int kNW = 16;    // wavefronts per workgroup
 
 // The operator's rows viewed as an n1 x n2 grid (row = i1 * n2 + i2), cut
-// into b1 x b2 blocks (b1 * b2 == kRB; edge blocks are partly empty).
+// into b1 x b2 blocks (b1 * b2 == kRB; edge blocks are partly empty). Within
+// a block, rows are numbered into the kernel's processing slots; a lane group
+// runs kQ consecutive slots in lockstep and a wavefront 4 * kQ, so
+// consecutive slots should be rows with the same amount of work per chunk. along_i1 numbers slots along i1
+// first (slot = r2 * b1 + r1), otherwise along i2 (slot = r1 * b2 + r2).
 struct RowGrid {
   int64_t n1 = 0, n2 = 0;
   int64_t b1 = 0, b2 = 0;
+  bool along_i1 = false;
 };
 
 struct Tiled {
-  int64_t nblk = 0, nchunk = 0, nnz = 0, ncols = 0;
+  int64_t nblk = 0, nchunk = 0, nnz = 0, ncols = 0;  // nnz counts padding entries
   int32_t *blk_rows = nullptr;     // [nblk * kRB], -1 where a block has no row
   int32_t *blk_chunk = nullptr;    // [nblk + 1]
   int32_t *chunk_cols = nullptr;   // [nchunk * kC]
   int32_t *chunk_ncols = nullptr;  // [nchunk]
   int32_t *chunk_ent = nullptr;    // [nchunk + 1] first entry of each chunk
-  int32_t *seg = nullptr;          // [nchunk * (kRB + 1)], offsets within the chunk
-  int32_t *ent_col = nullptr;      // [nnz] local column within the chunk
-  void *ent_w = nullptr;           // [nnz] weights in wdtype
+  int32_t *qseg = nullptr;         // [nchunk * (kNQ + 1)] quad offsets within the chunk
+  int32_t *ent_col = nullptr;      // [nnz] local column (kC = the all-zero padding column)
+  void *ent_w = nullptr;           // [nnz] weights in wdtype (0 for padding)
   srt_dtype wdtype = SRT_F32;
   double scale = 1.0;
   size_t bytes() const;
   void release();
 };
 
-// Builds the row-blocked format of a CSR operator (weights copied as stored).
-Status build_tiled(const Csr &m, const RowGrid &g, hipStream_t s, Tiled *out);
+// Builds the row-blocked format of a CSR operator (weights copied as stored);
+// chunks hold at most kC columns and max_ent entries after padding.
+Status build_tiled(const Csr &m, const RowGrid &g, int max_ent, hipStream_t s, Tiled *out);
 
 }  // namespace srt
 

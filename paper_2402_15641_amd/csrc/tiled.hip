@@ -8,19 +8,26 @@
 // heights, a compact tile of pixels or of rho-z cells) share most cells, so
 // the rows are grouped into geometrically compact blocks of kRB rows. One
 // workgroup owns a block and one slice of the dense index. It walks the union
-// of the block's columns in chunks of at most kC columns and kE entries; per
-// chunk it stages, in one batch of coalesced loads, the chunk's dense rows,
-// its entries and its per-row offsets into LDS, and every row of the block
-// then consumes them from LDS. The rows' accumulators stay in registers across
-// chunks, so every output element is written once, in a fixed summation order.
+// of the block's columns in chunks; per chunk it stages the chunk's dense
+// rows, entries and quad offsets into LDS, and every row of the block then
+// consumes them from LDS. The rows' accumulators stay in registers across
+// chunks, so every output element is written once, in a fixed order.
 //
-// Format (built on the device from the CSR operator):
-//   blk_rows[b*kRB + pos]         global row at block position pos (-1: none)
+// Quads: the kernel runs kQ rows ("a quad", consecutive block slots) in
+// lockstep on one lane group. Within a chunk the quad's row segments are
+// padded to the same length and interleaved (entry k of quad row j at
+// 4k + j), padding entries pointing at an all-zero LDS column (index kC) with
+// weight 0. Chunks are cut greedily along the block's ascending columns so
+// that both the column count (<= kC) and the padded entry count (<= max_ent)
+// fit the LDS budget.
+//
+// Format:
+//   blk_rows[b*kRB + slot]        global row at block slot (-1: none)
 //   blk_chunk[b] .. [b+1]         chunks of block b (consecutive ids)
 //   chunk_cols[c*kC + u]          global column of local column u of chunk c
 //   chunk_ncols[c]                columns in chunk c
-//   chunk_ent[c] .. [c+1]         entries of chunk c, ordered by row position
-//   seg[c*(kRB+1) + pos]          first entry of row pos, relative to chunk_ent[c]
+//   chunk_ent[c] .. [c+1]         padded entries of chunk c
+//   qseg[c*(kNQ+1) + q]           first entry of quad q, relative to chunk_ent[c]
 //   ent_col[e], ent_w[e]          local column and weight of entry e
 #include <hipcub/hipcub.hpp>
 
@@ -38,11 +45,11 @@ struct Buf {
   template <class T> T *as() const { return (T *)p; }
 };
 
-__device__ __forceinline__ void block_of(const RowGrid &g, int64_t row, int64_t *blk, int *pos) {
+__device__ __forceinline__ void block_of(const RowGrid &g, int64_t row, int64_t *blk, int *slot) {
   const int64_t i1 = row / g.n2, i2 = row - i1 * g.n2;
   const int64_t nb2 = (g.n2 + g.b2 - 1) / g.b2;
   *blk = (i1 / g.b1) * nb2 + i2 / g.b2;
-  *pos = (int)((i1 % g.b1) * g.b2 + i2 % g.b2);
+  *slot = g.along_i1 ? (int)((i2 % g.b2) * g.b1 + i1 % g.b1) : (int)((i1 % g.b1) * g.b2 + i2 % g.b2);
 }
 
 __device__ int64_t lower_bound_u64(const uint64_t *a, int64_t n, uint64_t v) {
@@ -59,20 +66,35 @@ __global__ void k_rows(const int32_t *__restrict__ rowptr, int64_t nrows, RowGri
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nrows) return;
   int64_t b;
-  int pos;
-  block_of(g, r, &b, &pos);
-  blk_rows[b * kRB + pos] = (int32_t)r;
+  int slot;
+  block_of(g, r, &b, &slot);
+  blk_rows[b * kRB + slot] = (int32_t)r;
   for (int32_t e = rowptr[r]; e < rowptr[r + 1]; ++e) row_of[e] = (int32_t)r;
 }
 
+// Key (block, column) and the entry's own index, to sort entries by block and column.
 __global__ void k_bc_keys(const int32_t *__restrict__ row_of, const int32_t *__restrict__ cols,
-                          int64_t nnz, RowGrid g, uint64_t *__restrict__ keys) {
+                          int64_t nnz, RowGrid g, uint64_t *__restrict__ keys,
+                          int32_t *__restrict__ idx) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= nnz) return;
   int64_t b;
-  int pos;
-  block_of(g, row_of[e], &b, &pos);
+  int slot;
+  block_of(g, row_of[e], &b, &slot);
   keys[e] = ((uint64_t)b << 32) | (uint32_t)cols[e];
+  idx[e] = (int32_t)e;
+}
+
+// Slot of every entry in (block, column) order.
+__global__ void k_sorted_slots(const int32_t *__restrict__ idx_sorted,
+                               const int32_t *__restrict__ row_of, int64_t nnz, RowGrid g,
+                               uint8_t *__restrict__ slot_sorted) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nnz) return;
+  int64_t b;
+  int slot;
+  block_of(g, row_of[idx_sorted[i]], &b, &slot);
+  slot_sorted[i] = (uint8_t)slot;
 }
 
 // ustart[b]: first distinct (block, col) key of block b, b in [0, nblk].
@@ -83,27 +105,58 @@ __global__ void k_ustart(const uint64_t *__restrict__ ukeys, int64_t nu, int64_t
   ustart[b] = lower_bound_u64(ukeys, nu, (uint64_t)b << 32);
 }
 
-// Greedy cut of each block's distinct columns (ascending) into chunks of at
-// most kC columns and kE entries. One thread per block.
-__global__ void k_chunking(const int64_t *__restrict__ ustart, const int32_t *__restrict__ ucount,
-                           int64_t nblk, int32_t *__restrict__ uchunk, int32_t *__restrict__ ulocal,
-                           int64_t *__restrict__ nch) {
+// Greedy cut of each block's distinct columns (ascending) into chunks with at
+// most kC columns and at most max_ent entries once every quad's rows are
+// padded to the quad's longest segment. One thread per block; per-slot counts
+// and per-quad maxima of the open chunk live in LDS.
+constexpr int kChunkThreads = 32;
+__global__ __launch_bounds__(kChunkThreads) void k_chunking(
+    const int64_t *__restrict__ ustart, const int32_t *__restrict__ ucount,
+    const int64_t *__restrict__ upos, const uint8_t *__restrict__ slot_sorted, int64_t nblk,
+    int max_ent, int32_t *__restrict__ uchunk, int32_t *__restrict__ ulocal,
+    int64_t *__restrict__ nch) {
+  __shared__ uint16_t cnt_all[kChunkThreads][kRB];
+  __shared__ uint16_t qmax_all[kChunkThreads][kNQ];
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b > nblk) return;
   if (b == nblk) {
     nch[b] = 0;
     return;
   }
-  int32_t chunk = 0, ncol = 0, nent = 0;
+  uint16_t *cnt = cnt_all[threadIdx.x];
+  uint16_t *qmax = qmax_all[threadIdx.x];
+  for (int i = 0; i < kRB; ++i) cnt[i] = 0;
+  for (int i = 0; i < kNQ; ++i) qmax[i] = 0;
+  int32_t chunk = 0, ncol = 0, padded = 0;
   for (int64_t j = ustart[b]; j < ustart[b + 1]; ++j) {
-    if (ncol == kC || nent + ucount[j] > kE) {
-      ++chunk;
-      ncol = 0;
-      nent = 0;
+    // Add column j to the open chunk; if that breaks a limit, close the chunk
+    // and open a new one holding column j alone (that always fits: at most
+    // one entry per row, so at most kQ padded entries per touched quad).
+    bool again = true;
+    while (again) {
+      again = false;
+      int add = 0;
+      for (int64_t i = upos[j]; i < upos[j] + ucount[j]; ++i) {
+        const int sl = slot_sorted[i], q = sl / kQ;
+        const int c1 = ++cnt[sl];
+        if (c1 > qmax[q]) {
+          add += kQ * (c1 - qmax[q]);
+          qmax[q] = (uint16_t)c1;
+        }
+      }
+      if (ncol > 0 && (ncol + 1 > kC || padded + add > max_ent)) {
+        for (int i = 0; i < kRB; ++i) cnt[i] = 0;
+        for (int i = 0; i < kNQ; ++i) qmax[i] = 0;
+        ++chunk;
+        ncol = 0;
+        padded = 0;
+        again = true;
+      } else {
+        padded += add;
+      }
     }
     uchunk[j] = chunk;
     ulocal[j] = ncol++;
-    nent += ucount[j];
   }
   nch[b] = ustart[b + 1] > ustart[b] ? chunk + 1 : 0;
 }
@@ -126,48 +179,83 @@ __global__ void k_blk_chunk(const int64_t *__restrict__ chunk0, int64_t nblk,
   if (b <= nblk) blk_chunk[b] = (int32_t)chunk0[b];
 }
 
-__global__ void k_entry_keys(const int32_t *__restrict__ row_of, const uint64_t *__restrict__ bc,
-                             int64_t nnz, RowGrid g, const uint64_t *__restrict__ ukeys,
-                             const int64_t *__restrict__ ustart, const int64_t *__restrict__ chunk0,
-                             const int32_t *__restrict__ uchunk, const int32_t *__restrict__ ulocal,
-                             uint64_t *__restrict__ key2, int32_t *__restrict__ local,
-                             int32_t *__restrict__ idx) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nnz) return;
-  int64_t b;
-  int pos;
-  block_of(g, row_of[e], &b, &pos);
-  const int64_t j = ustart[b] + lower_bound_u64(ukeys + ustart[b], ustart[b + 1] - ustart[b], bc[e]);
+// For the entries of distinct key j (contiguous in (block, column) order):
+// chunk, local column and the (chunk, slot) sort key.
+__global__ void k_entry_keys(const uint64_t *__restrict__ ukeys, const int32_t *__restrict__ ucount,
+                             const int64_t *__restrict__ upos, int64_t nu,
+                             const int64_t *__restrict__ chunk0, const int32_t *__restrict__ uchunk,
+                             const int32_t *__restrict__ ulocal,
+                             const uint8_t *__restrict__ slot_sorted, uint64_t *__restrict__ key2,
+                             int32_t *__restrict__ local, int32_t *__restrict__ seq) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nu) return;
+  const int64_t b = (int64_t)(ukeys[j] >> 32);
   const int64_t c = chunk0[b] + uchunk[j];
-  local[e] = ulocal[j];
-  key2[e] = (uint64_t)c * kRB + (uint64_t)pos;
-  idx[e] = (int32_t)e;
+  for (int64_t i = upos[j]; i < upos[j] + ucount[j]; ++i) {
+    key2[i] = (uint64_t)c * kRB + slot_sorted[i];
+    local[i] = ulocal[j];
+    seq[i] = (int32_t)i;
+  }
 }
 
+// rawstart[sid] = first entry of segment sid = chunk * kRB + slot.
+__global__ void k_rawstart(const uint64_t *__restrict__ key2s, int64_t nnz, int64_t nseg,
+                           int64_t *__restrict__ rawstart) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t > nseg) return;
+  rawstart[t] = lower_bound_u64(key2s, nnz, (uint64_t)t);
+}
+
+// Padded length of quad (chunk, q): kQ times its longest row segment.
+__global__ void k_quad_len(const int64_t *__restrict__ rawstart, int64_t nquad,
+                           int64_t *__restrict__ qlen) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t > nquad) return;
+  if (t == nquad) {
+    qlen[t] = 0;
+    return;
+  }
+  int64_t m = 0;
+  for (int j = 0; j < kQ; ++j) {
+    const int64_t len = rawstart[t * kQ + j + 1] - rawstart[t * kQ + j];
+    m = len > m ? len : m;
+  }
+  qlen[t] = kQ * m;
+}
+
+__global__ void k_chunk_meta2(const int64_t *__restrict__ qstart, int64_t nchunk,
+                              int32_t *__restrict__ chunk_ent, int32_t *__restrict__ qseg) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < nchunk * (kNQ + 1)) {
+    const int64_t c = t / (kNQ + 1), q = t % (kNQ + 1);
+    qseg[t] = (int32_t)(qstart[c * kNQ + q] - qstart[c * kNQ]);
+  }
+  if (t <= nchunk) chunk_ent[t] = (int32_t)qstart[t * kNQ];
+}
+
+__global__ void k_pad_fill(int64_t n, int32_t *__restrict__ ent_col) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) ent_col[i] = kC;
+}
+
+// Entry i (in (chunk, slot) order) goes to row j = slot % kQ of its quad at
+// padded position kQ * k + j, k = its rank within the row segment.
 template <typename W>
-__global__ void k_gather(const int32_t *__restrict__ perm, int64_t nnz,
-                         const int32_t *__restrict__ local, const W *__restrict__ vals,
-                         int32_t *__restrict__ ent_col, W *__restrict__ ent_w) {
+__global__ void k_scatter(const uint64_t *__restrict__ key2s, const int32_t *__restrict__ perm2,
+                          int64_t nnz, const int64_t *__restrict__ rawstart,
+                          const int64_t *__restrict__ qstart, const int32_t *__restrict__ local,
+                          const int32_t *__restrict__ idx_sorted, const W *__restrict__ vals,
+                          int32_t *__restrict__ ent_col, W *__restrict__ ent_w) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nnz) return;
-  const int32_t e = perm[i];
-  ent_col[i] = local[e];
-  ent_w[i] = vals[e];
-}
-
-__global__ void k_chunk_ent(const uint64_t *__restrict__ key2s, int64_t nnz, int64_t nchunk,
-                            int32_t *__restrict__ chunk_ent) {
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c > nchunk) return;
-  chunk_ent[c] = (int32_t)lower_bound_u64(key2s, nnz, (uint64_t)c * kRB);
-}
-
-__global__ void k_seg(const uint64_t *__restrict__ key2s, int64_t nnz, int64_t nchunk,
-                      const int32_t *__restrict__ chunk_ent, int32_t *__restrict__ seg) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nchunk * (kRB + 1)) return;
-  const int64_t c = t / (kRB + 1), p = t % (kRB + 1);
-  seg[t] = (int32_t)(lower_bound_u64(key2s, nnz, (uint64_t)c * kRB + (uint64_t)p) - chunk_ent[c]);
+  const int64_t sid = (int64_t)key2s[i];
+  const int64_t c = sid / kRB;
+  const int slot = (int)(sid % kRB);
+  const int64_t k = i - rawstart[sid];
+  const int64_t dst = qstart[c * kNQ + slot / kQ] + kQ * k + slot % kQ;
+  const int32_t src = perm2[i];  // position in (block, column) order
+  ent_col[dst] = local[src];
+  ent_w[dst] = vals[idx_sorted[src]];
 }
 
 int bits_for(uint64_t v) {
@@ -176,8 +264,8 @@ int bits_for(uint64_t v) {
   return b;
 }
 
-template <typename F>
-Status scan_i64(const int64_t *in, int64_t *out, int64_t n, hipStream_t s, F oom) {
+template <typename In, typename F>
+Status scan_to_i64(const In *in, int64_t *out, int64_t n, hipStream_t s, F oom) {
   size_t b = 0;
   Buf tmp;
   SRT_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, b, in, out, (int)n, s));
@@ -190,38 +278,41 @@ Status scan_i64(const int64_t *in, int64_t *out, int64_t n, hipStream_t s, F oom
 
 size_t Tiled::bytes() const {
   return sizeof(int32_t) * ((size_t)nblk * kRB + nblk + 1 + (size_t)nchunk * (kC + 1) + nchunk + 1 +
-                            (size_t)nchunk * (kRB + 1) + (size_t)nnz) +
+                            (size_t)nchunk * (kNQ + 1) + (size_t)nnz) +
          dtype_size(wdtype) * (size_t)nnz;
 }
 
 void Tiled::release() {
   for (void *p : {(void *)blk_rows, (void *)blk_chunk, (void *)chunk_cols, (void *)chunk_ncols,
-                  (void *)chunk_ent, (void *)seg, (void *)ent_col, ent_w})
+                  (void *)chunk_ent, (void *)qseg, (void *)ent_col, ent_w})
     (void)hipFree(p);
   *this = Tiled{};
 }
 
-Status build_tiled(const Csr &m, const RowGrid &g, hipStream_t s, Tiled *out) {
-  if (g.n1 * g.n2 != m.nrows || g.b1 * g.b2 != kRB)
+Status build_tiled(const Csr &m, const RowGrid &g, int max_ent, hipStream_t s, Tiled *out) {
+  if (g.n1 * g.n2 != m.nrows || g.b1 * g.b2 != kRB || max_ent < kRB)
     return fail(SRT_EDEVICE, "row grid does not match the operator");
   const int64_t nnz = m.nnz, nrows = m.nrows;
   const int64_t nblk = ((g.n1 + g.b1 - 1) / g.b1) * ((g.n2 + g.b2 - 1) / g.b2);
   const int t = 256;
   Tiled &T = *out;
   T.nblk = nblk;
-  T.nnz = nnz;
   T.wdtype = m.wdtype;
   T.scale = m.scale;
   T.ncols = m.ncols;
   auto oom = [] { return fail(SRT_ENOMEM, "device allocation for the tiled operator failed"); };
+  if (nnz >= INT32_MAX / 2) return fail(SRT_ENOTSUP, "operator too large for the tiled format");
   if (hipMalloc(&T.blk_rows, sizeof(int32_t) * (nblk > 0 ? nblk * kRB : 1)) != hipSuccess ||
       hipMalloc(&T.blk_chunk, sizeof(int32_t) * (nblk + 1)) != hipSuccess)
     return oom();
   if (nblk > 0) SRT_HIP(hipMemsetAsync(T.blk_rows, 0xff, sizeof(int32_t) * nblk * kRB, s));
 
-  Buf row_of, bc, bc_sorted, ukeys, ucount, nu_d, ustart, uchunk, ulocal, nch, chunk0;
-  if (row_of.alloc(4 * nnz) || bc.alloc(8 * nnz) || bc_sorted.alloc(8 * nnz) ||
-      ukeys.alloc(8 * nnz) || ucount.alloc(4 * nnz) || nu_d.alloc(8) ||
+  // 1. entries in (block, column) order, with their slots
+  Buf row_of, bc, bc_sorted, idx, idx_sorted, slot_sorted, ukeys, ucount, upos, nu_d, ustart,
+      uchunk, ulocal, nch, chunk0;
+  if (row_of.alloc(4 * nnz) || bc.alloc(8 * nnz) || bc_sorted.alloc(8 * nnz) || idx.alloc(4 * nnz) ||
+      idx_sorted.alloc(4 * nnz) || slot_sorted.alloc(nnz) || ukeys.alloc(8 * nnz) ||
+      ucount.alloc(4 * (nnz + 1)) || upos.alloc(8 * (nnz + 1)) || nu_d.alloc(8) ||
       ustart.alloc(8 * (nblk + 1)) || uchunk.alloc(4 * nnz) || ulocal.alloc(4 * nnz) ||
       nch.alloc(8 * (nblk + 1)) || chunk0.alloc(8 * (nblk + 1)))
     return oom();
@@ -231,42 +322,48 @@ Status build_tiled(const Csr &m, const RowGrid &g, hipStream_t s, Tiled *out) {
   int64_t nu = 0;
   if (nnz > 0) {
     hipLaunchKernelGGL(k_bc_keys, dim3(nblocks(nnz, t)), dim3(t), 0, s, row_of.as<int32_t>(),
-                       m.cols, nnz, g, bc.as<uint64_t>());
+                       m.cols, nnz, g, bc.as<uint64_t>(), idx.as<int32_t>());
     const int kbits = 32 + bits_for((uint64_t)nblk);
     size_t b1 = 0, b2 = 0;
     Buf tmp;
-    SRT_HIP(hipcub::DeviceRadixSort::SortKeys(nullptr, b1, bc.as<uint64_t>(),
-                                              bc_sorted.as<uint64_t>(), (int)nnz, 0, kbits, s));
+    SRT_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, b1, bc.as<uint64_t>(),
+                                               bc_sorted.as<uint64_t>(), idx.as<int32_t>(),
+                                               idx_sorted.as<int32_t>(), (int)nnz, 0, kbits, s));
     SRT_HIP(hipcub::DeviceRunLengthEncode::Encode(nullptr, b2, bc_sorted.as<uint64_t>(),
                                                   ukeys.as<uint64_t>(), ucount.as<int32_t>(),
                                                   nu_d.as<int64_t>(), (int)nnz, s));
     if (tmp.alloc(b1 > b2 ? b1 : b2)) return oom();
-    SRT_HIP(hipcub::DeviceRadixSort::SortKeys(tmp.p, b1, bc.as<uint64_t>(),
-                                              bc_sorted.as<uint64_t>(), (int)nnz, 0, kbits, s));
+    SRT_HIP(hipcub::DeviceRadixSort::SortPairs(tmp.p, b1, bc.as<uint64_t>(),
+                                               bc_sorted.as<uint64_t>(), idx.as<int32_t>(),
+                                               idx_sorted.as<int32_t>(), (int)nnz, 0, kbits, s));
     SRT_HIP(hipcub::DeviceRunLengthEncode::Encode(tmp.p, b2, bc_sorted.as<uint64_t>(),
                                                   ukeys.as<uint64_t>(), ucount.as<int32_t>(),
                                                   nu_d.as<int64_t>(), (int)nnz, s));
     SRT_HIP(hipMemcpyAsync(&nu, nu_d.p, 8, hipMemcpyDeviceToHost, s));
     SRT_HIP(hipStreamSynchronize(s));
+    hipLaunchKernelGGL(k_sorted_slots, dim3(nblocks(nnz, t)), dim3(t), 0, s,
+                       idx_sorted.as<int32_t>(), row_of.as<int32_t>(), nnz, g,
+                       slot_sorted.as<uint8_t>());
+    SRT_TRY(scan_to_i64(ucount.as<int32_t>(), upos.as<int64_t>(), nu, s, oom));
   }
+  // 2. chunks
   hipLaunchKernelGGL(k_ustart, dim3(nblocks(nblk + 1, t)), dim3(t), 0, s, ukeys.as<uint64_t>(), nu,
                      nblk, ustart.as<int64_t>());
-  hipLaunchKernelGGL(k_chunking, dim3(nblocks(nblk + 1, 64)), dim3(64), 0, s, ustart.as<int64_t>(),
-                     ucount.as<int32_t>(), nblk, uchunk.as<int32_t>(), ulocal.as<int32_t>(),
-                     nch.as<int64_t>());
-  SRT_TRY(scan_i64(nch.as<int64_t>(), chunk0.as<int64_t>(), nblk + 1, s, oom));
+  hipLaunchKernelGGL(k_chunking, dim3(nblocks(nblk + 1, kChunkThreads)), dim3(kChunkThreads), 0, s,
+                     ustart.as<int64_t>(), ucount.as<int32_t>(), upos.as<int64_t>(),
+                     slot_sorted.as<uint8_t>(), nblk, max_ent, uchunk.as<int32_t>(),
+                     ulocal.as<int32_t>(), nch.as<int64_t>());
+  SRT_TRY(scan_to_i64(nch.as<int64_t>(), chunk0.as<int64_t>(), nblk + 1, s, oom));
   int64_t nchunk = 0;
   SRT_HIP(hipMemcpyAsync(&nchunk, chunk0.as<int64_t>() + nblk, 8, hipMemcpyDeviceToHost, s));
   SRT_HIP(hipStreamSynchronize(s));
-  if (nchunk * (kRB + 1) >= INT32_MAX || nchunk * kC >= INT32_MAX)
+  if (nchunk * (kNQ + 1) >= INT32_MAX || nchunk * kC >= INT32_MAX || nchunk * kRB >= INT32_MAX)
     return fail(SRT_ENOTSUP, "too many operator chunks");
   T.nchunk = nchunk;
   if (hipMalloc(&T.chunk_cols, sizeof(int32_t) * (nchunk > 0 ? nchunk * kC : 1)) != hipSuccess ||
       hipMalloc(&T.chunk_ncols, sizeof(int32_t) * (nchunk > 0 ? nchunk : 1)) != hipSuccess ||
       hipMalloc(&T.chunk_ent, sizeof(int32_t) * (nchunk + 1)) != hipSuccess ||
-      hipMalloc(&T.seg, sizeof(int32_t) * (nchunk > 0 ? nchunk * (kRB + 1) : 1)) != hipSuccess ||
-      hipMalloc(&T.ent_col, sizeof(int32_t) * (nnz > 0 ? nnz : 1)) != hipSuccess ||
-      hipMalloc(&T.ent_w, dtype_size(m.wdtype) * (nnz > 0 ? nnz : 1)) != hipSuccess)
+      hipMalloc(&T.qseg, sizeof(int32_t) * (nchunk > 0 ? nchunk * (kNQ + 1) : 1)) != hipSuccess)
     return oom();
   if (nchunk > 0) {
     SRT_HIP(hipMemsetAsync(T.chunk_cols, 0, sizeof(int32_t) * nchunk * kC, s));
@@ -278,47 +375,70 @@ Status build_tiled(const Csr &m, const RowGrid &g, hipStream_t s, Tiled *out) {
     hipLaunchKernelGGL(k_chunk_cols, dim3(nblocks(nu, t)), dim3(t), 0, s, ukeys.as<uint64_t>(), nu,
                        chunk0.as<int64_t>(), uchunk.as<int32_t>(), ulocal.as<int32_t>(),
                        T.chunk_cols, T.chunk_ncols);
-  Buf key2, key2s, local, idx, perm;
+  // 3. entries in (chunk, slot) order and their padded quad positions
+  const int64_t nseg = nchunk * kRB, nquad = nchunk * kNQ;
+  Buf key2, key2s, local, seq, perm2, rawstart, qlen, qstart;
+  if (key2.alloc(8 * nnz) || key2s.alloc(8 * nnz) || local.alloc(4 * nnz) || seq.alloc(4 * nnz) ||
+      perm2.alloc(4 * nnz) || rawstart.alloc(8 * (nseg + 1)) || qlen.alloc(8 * (nquad + 1)) ||
+      qstart.alloc(8 * (nquad + 1)))
+    return oom();
   if (nnz > 0) {
-    if (key2.alloc(8 * nnz) || key2s.alloc(8 * nnz) || local.alloc(4 * nnz) || idx.alloc(4 * nnz) ||
-        perm.alloc(4 * nnz))
-      return oom();
-    hipLaunchKernelGGL(k_entry_keys, dim3(nblocks(nnz, t)), dim3(t), 0, s, row_of.as<int32_t>(),
-                       bc.as<uint64_t>(), nnz, g, ukeys.as<uint64_t>(), ustart.as<int64_t>(),
-                       chunk0.as<int64_t>(), uchunk.as<int32_t>(), ulocal.as<int32_t>(),
-                       key2.as<uint64_t>(), local.as<int32_t>(), idx.as<int32_t>());
-    const int kbits = bits_for((uint64_t)nchunk * kRB + kRB);
+    hipLaunchKernelGGL(k_entry_keys, dim3(nblocks(nu, t)), dim3(t), 0, s, ukeys.as<uint64_t>(),
+                       ucount.as<int32_t>(), upos.as<int64_t>(), nu, chunk0.as<int64_t>(),
+                       uchunk.as<int32_t>(), ulocal.as<int32_t>(), slot_sorted.as<uint8_t>(),
+                       key2.as<uint64_t>(), local.as<int32_t>(), seq.as<int32_t>());
+    const int kbits = bits_for((uint64_t)nseg + kRB);
     size_t b = 0;
     Buf tmp3;
     SRT_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, b, key2.as<uint64_t>(), key2s.as<uint64_t>(),
-                                               idx.as<int32_t>(), perm.as<int32_t>(), (int)nnz, 0,
+                                               seq.as<int32_t>(), perm2.as<int32_t>(), (int)nnz, 0,
                                                kbits, s));
     if (tmp3.alloc(b)) return oom();
     SRT_HIP(hipcub::DeviceRadixSort::SortPairs(tmp3.p, b, key2.as<uint64_t>(), key2s.as<uint64_t>(),
-                                               idx.as<int32_t>(), perm.as<int32_t>(), (int)nnz, 0,
+                                               seq.as<int32_t>(), perm2.as<int32_t>(), (int)nnz, 0,
                                                kbits, s));
-    switch (dtype_size(m.wdtype)) {
+  }
+  hipLaunchKernelGGL(k_rawstart, dim3(nblocks(nseg + 1, t)), dim3(t), 0, s, key2s.as<uint64_t>(), nnz,
+                     nseg, rawstart.as<int64_t>());
+  hipLaunchKernelGGL(k_quad_len, dim3(nblocks(nquad + 1, t)), dim3(t), 0, s, rawstart.as<int64_t>(),
+                     nquad, qlen.as<int64_t>());
+  SRT_TRY(scan_to_i64(qlen.as<int64_t>(), qstart.as<int64_t>(), nquad + 1, s, oom));
+  int64_t npad = 0;
+  SRT_HIP(hipMemcpyAsync(&npad, qstart.as<int64_t>() + nquad, 8, hipMemcpyDeviceToHost, s));
+  SRT_HIP(hipStreamSynchronize(s));
+  if (npad >= INT32_MAX) return fail(SRT_ENOTSUP, "too many padded operator entries");
+  T.nnz = npad;
+  const size_t wsz = dtype_size(m.wdtype);
+  if (hipMalloc(&T.ent_col, sizeof(int32_t) * (npad > 0 ? npad : 1)) != hipSuccess ||
+      hipMalloc(&T.ent_w, wsz * (npad > 0 ? npad : 1)) != hipSuccess)
+    return oom();
+  if (npad > 0) {
+    hipLaunchKernelGGL(k_pad_fill, dim3(nblocks(npad, t)), dim3(t), 0, s, npad, T.ent_col);
+    SRT_HIP(hipMemsetAsync(T.ent_w, 0, wsz * npad, s));
+  }
+  hipLaunchKernelGGL(k_chunk_meta2, dim3(nblocks(nchunk * (kNQ + 1) + 1, t)), dim3(t), 0, s,
+                     qstart.as<int64_t>(), nchunk, T.chunk_ent, T.qseg);
+  if (nnz > 0) {
+    switch (wsz) {
       case 8:
-        hipLaunchKernelGGL(k_gather<uint64_t>, dim3(nblocks(nnz, t)), dim3(t), 0, s,
-                           perm.as<int32_t>(), nnz, local.as<int32_t>(), (const uint64_t *)m.vals,
-                           T.ent_col, (uint64_t *)T.ent_w);
+        hipLaunchKernelGGL(k_scatter<uint64_t>, dim3(nblocks(nnz, t)), dim3(t), 0, s,
+                           key2s.as<uint64_t>(), perm2.as<int32_t>(), nnz, rawstart.as<int64_t>(),
+                           qstart.as<int64_t>(), local.as<int32_t>(), idx_sorted.as<int32_t>(),
+                           (const uint64_t *)m.vals, T.ent_col, (uint64_t *)T.ent_w);
         break;
       case 4:
-        hipLaunchKernelGGL(k_gather<uint32_t>, dim3(nblocks(nnz, t)), dim3(t), 0, s,
-                           perm.as<int32_t>(), nnz, local.as<int32_t>(), (const uint32_t *)m.vals,
-                           T.ent_col, (uint32_t *)T.ent_w);
+        hipLaunchKernelGGL(k_scatter<uint32_t>, dim3(nblocks(nnz, t)), dim3(t), 0, s,
+                           key2s.as<uint64_t>(), perm2.as<int32_t>(), nnz, rawstart.as<int64_t>(),
+                           qstart.as<int64_t>(), local.as<int32_t>(), idx_sorted.as<int32_t>(),
+                           (const uint32_t *)m.vals, T.ent_col, (uint32_t *)T.ent_w);
         break;
       default:
-        hipLaunchKernelGGL(k_gather<uint16_t>, dim3(nblocks(nnz, t)), dim3(t), 0, s,
-                           perm.as<int32_t>(), nnz, local.as<int32_t>(), (const uint16_t *)m.vals,
-                           T.ent_col, (uint16_t *)T.ent_w);
+        hipLaunchKernelGGL(k_scatter<uint16_t>, dim3(nblocks(nnz, t)), dim3(t), 0, s,
+                           key2s.as<uint64_t>(), perm2.as<int32_t>(), nnz, rawstart.as<int64_t>(),
+                           qstart.as<int64_t>(), local.as<int32_t>(), idx_sorted.as<int32_t>(),
+                           (const uint16_t *)m.vals, T.ent_col, (uint16_t *)T.ent_w);
     }
   }
-  hipLaunchKernelGGL(k_chunk_ent, dim3(nblocks(nchunk + 1, t)), dim3(t), 0, s, key2s.as<uint64_t>(),
-                     nnz, nchunk, T.chunk_ent);
-  if (nchunk > 0)
-    hipLaunchKernelGGL(k_seg, dim3(nblocks(nchunk * (kRB + 1), t)), dim3(t), 0, s,
-                       key2s.as<uint64_t>(), nnz, nchunk, T.chunk_ent, T.seg);
   SRT_HIP(hipGetLastError());
   SRT_HIP(hipStreamSynchronize(s));
   return Status{};
