@@ -1,0 +1,91 @@
+"""Serving benchmark: p50/p99 latency and throughput of a mixed request stream.
+
+Workload: grids drawn uniformly from 64^3, 128^3 and 192^3 on [-1,1]^3,
+apertures N columns x N heights x 4N radii on a cylinder of radius 1.3
+(l_max = distance to the farthest voxel corner); 70% forward requests
+(ellipsoid phantoms, 16 per grid, seeded) and 30% adjoint requests (N(0,1)
+data, 16 per grid); Poisson arrivals at each rate; plans resident on the
+device; admission by device-memory footprint (default budget 16 GiB);
+continuous batching (up to 8 per batch) on 4 streams. Run once with FP32
+operator weights and once with BF16 weights (FP32 accumulation).
+
+    python -m paper_2402_15641_amd.serve_bench [--rates 50 100 ...] [--weights f32 bf16]
+
+Prints one JSON line per (weights, rate).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+
+import numpy as np
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--rates", type=float, nargs="+", default=[50, 100, 200, 500, 1000, 2000])
+    ap.add_argument("--weights", nargs="+", default=["f32", "bf16"])
+    ap.add_argument("--max-requests", type=int, default=5000)
+    ap.add_argument("--seconds", type=float, default=10.0,
+                    help="trace length per rate is min(max_requests, rate * seconds)")
+    ap.add_argument("--budget-gib", type=float, default=16.0)
+    ap.add_argument("--sizes", type=int, nargs="+", default=[64, 128, 192])
+    args = ap.parse_args()
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    sys.path.insert(0, root)
+    import torch
+    from srt_inputs import config, phantoms
+    from paper_2402_15641_amd import SRTPlan
+    from paper_2402_15641_amd.serve import (GpuExecutor, Request, Scheduler, latency_stats,
+                                            plan_footprint_fn, serve)
+
+    pools = {}
+    aps = {n: config(f"cfg5_{n}") for n in args.sizes}
+    for n, a in aps.items():
+        vols = [torch.from_numpy(phantoms.ellipsoid_phantom(a, np.random.default_rng(5000 + 100 * n + i),
+                                                            noise_rng=np.random.default_rng(6000 + 100 * n + i))
+                                 ).float().cuda() for i in range(16)]
+        dats = [torch.from_numpy(np.random.default_rng(7000 + 100 * n + i).standard_normal(a.data_shape)
+                                 ).float().cuda() for i in range(16)]
+        pools[n] = (vols, dats)
+    for w in args.weights:
+        plans = {f"n{n}": SRTPlan.from_geometry(a, value_dtype="f32", weight_dtype=w)
+                 for n, a in aps.items()}
+        fp = plan_footprint_fn(plans)
+        # warm up every (plan, direction, batch size) once
+        for key, p in plans.items():
+            n = int(key[1:])
+            for b in (1, 8):
+                p.forward(torch.stack(pools[n][0][:b]))
+                p.adjoint(torch.stack(pools[n][1][:b]))
+        torch.cuda.synchronize()
+        for rate in args.rates:
+            rng = np.random.default_rng(int(rate) + (0 if w == "f32" else 1))
+            nreq = int(min(args.max_requests, max(200, rate * args.seconds)))
+            t = np.cumsum(rng.exponential(1.0 / rate, nreq))
+            reqs = []
+            for i in range(nreq):
+                n = args.sizes[rng.integers(len(args.sizes))]
+                kind = "fwd" if rng.random() < 0.7 else "adj"
+                payload = pools[n][0 if kind == "fwd" else 1][rng.integers(16)]
+                reqs.append(Request(i, f"n{n}", kind, payload, float(t[i])))
+            sched = Scheduler(fp, int(args.budget_gib * (1 << 30)), max_batch=8, max_inflight=4)
+            ex = GpuExecutor(plans, n_streams=4)
+            done = serve(reqs, sched, ex)
+            torch.cuda.synchronize()
+            st = latency_stats(done)
+            st.update({"weights": w, "rate_rps": rate, "requests": nreq,
+                       "peak_in_use_gib": sched.peak_in_use / (1 << 30),
+                       "rejected": len(sched.rejected)})
+            print(json.dumps(st), flush=True)
+            for r in done:  # drop results before the next rate
+                r.result = None
+        for p in plans.values():
+            p.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,50 @@
+"""Serving on the device: results are bitwise the same alone and in the mix.
+
+Two small grids (16^3 and 24^3 voxels, cylinder radius 1.3, N columns x N
+heights x 4N radii), a Poisson stream of 48 mixed requests (70% forward,
+30% adjoint) arriving faster than they complete, device-memory admission
+with a budget that holds a few batches at a time.
+"""
+import numpy as np
+import pytest
+
+from srt_inputs import cylinder_aperture
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def test_results_alone_equal_results_in_the_mix():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm device")
+    from paper_2402_15641_amd import SRTPlan
+    from paper_2402_15641_amd.serve import (GpuExecutor, Request, Scheduler, latency_stats,
+                                            plan_footprint_fn, serve)
+    plans = {}
+    for n in (16, 24):
+        ap = cylinder_aperture(f"n{n}", n, 1.0, 1.3, n, n, 4 * n)
+        plans[f"n{n}"] = SRTPlan.from_geometry(ap, value_dtype="f32")
+    rng = np.random.default_rng(5)
+    reqs = []
+    t = 0.0
+    for i in range(48):
+        key = ("n16", "n24")[rng.integers(2)]
+        kind = "fwd" if rng.random() < 0.7 else "adj"
+        p = plans[key]
+        shape = p.vol_shape if kind == "fwd" else p.data_shape
+        payload = torch.from_numpy(rng.standard_normal(shape)).float().cuda()
+        t += rng.exponential(1.0 / 4000.0)
+        reqs.append(Request(i, key, kind, payload, t))
+    fp = plan_footprint_fn(plans)
+    budget = 3 * fp("n24", "adj", 2)
+    sched = Scheduler(fp, budget, max_batch=4, max_inflight=3)
+    done = serve(reqs, sched, GpuExecutor(plans, n_streams=3))
+    torch.cuda.synchronize()
+    assert len(done) == 48 and not sched.rejected
+    assert sched.peak_in_use <= budget
+    for r in done:
+        p = plans[r.plan]
+        alone = p.forward(r.payload) if r.kind == "fwd" else p.adjoint(r.payload)
+        assert torch.equal(alone, r.result), r.rid
+    st = latency_stats(done)
+    assert st["n"] == 48 and st["p99_ms"] >= st["p50_ms"] > 0
