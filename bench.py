@@ -38,7 +38,7 @@ sys.path.insert(0, ROOT)
 METRIC = "SRT fwd+adjoint pairs/s at 256^3, HBM GB/s % of peak; serving p50/p99 latency"
 PEAK_FP32_VALU_TFLOPS = 157.3  # MI355X FP32 vector: 256 CUs x 128 FMA/clk x 2 FLOP x 2.4 GHz
 PEAK_HBM_GBPS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stage_kernels_cfg3.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stage_kernels_pact256.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2402_15641_amd", "csrc", f)
                   for f in ("apply.hip", "srt_internal.h")]
 
@@ -108,10 +108,11 @@ def main():
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--weights", default="f32", choices=["f32", "bf16", "f16"])
-    p.add_argument("--workload", default="cfg3", choices=["cfg3", "cfg2"])
+    p.add_argument("--workload", default="pact256", choices=["pact256", "grid128"])
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--profile-copy", action="store_true",
-                   help="also run one 1 GiB device copy (counter calibration)")
+                   help="also run one 1 GiB read + 1 GiB write kernel (torch.neg; counter "
+                        "calibration for FETCH_SIZE / WRITE_SIZE)")
     args = p.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU "
@@ -126,9 +127,8 @@ def main():
         log("bench.py needs a ROCm device")
         sys.exit(1)
     ap = config(args.workload)
-    cfg_num = 3 if args.workload == "cfg3" else 2
     t0 = time.perf_counter()
-    F64 = phantoms.phantom(ap, cfg_num)
+    F64 = phantoms.phantom(ap)
     log(f"phantom {time.perf_counter() - t0:.1f} s")
     vol = torch.from_numpy(F64).float().cuda()
     F_in = vol.double().cpu().numpy()
@@ -147,7 +147,7 @@ def main():
     if args.profile_copy:
         src = torch.ones(1 << 28, device="cuda")  # 1 GiB of FP32
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        torch.neg(src, out=dst)  # a kernel of its own name: reads 1 GiB, writes 1 GiB
         torch.cuda.synchronize()
         del src, dst
 
@@ -206,7 +206,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: " + ("256^3 voxels at 0.1 mm, R=15.36 mm, "
                                                         "512 columns x 256 heights x 1024 radii"
-                                                        if args.workload == "cfg3" else
+                                                        if args.workload == "pact256" else
                                                         "128^3 on [-1,1]^3, R=1.3, 128 x 128 x 512"),
                    "batch": 1, "weights": args.weights, "phantom": "seeded",
                    "nnz_a12": nnz12, "nnz_a34": nnz34, "plan_build_s": round(t_plan, 3)},

@@ -140,12 +140,17 @@ class SimExecutor:
 class GpuExecutor:
     """Runs batches through the C ABI on a pool of HIP streams (all at the
     default priority). Inputs are stacked into one device buffer per batch,
-    the apply is launched on the batch's stream, and an event marks its end."""
+    the apply is launched on the batch's stream, and an event marks its end.
 
-    def __init__(self, plans: Dict[str, Any], n_streams: int = 4):
+    With keep_results a finished request carries its output as a device
+    tensor (a view of the batch output); without it the output is released
+    at completion, as a server that has handed the result on would."""
+
+    def __init__(self, plans: Dict[str, Any], n_streams: int = 4, keep_results: bool = True):
         import torch
         self.torch = torch
         self.plans = plans
+        self.keep_results = keep_results
         self.streams = [torch.cuda.Stream() for _ in range(n_streams)]
         self.free = list(range(n_streams))
         self.inflight: list = []
@@ -181,7 +186,7 @@ class GpuExecutor:
                 t = self.clock()
                 for i, r in enumerate(b.reqs):
                     r.finish = t
-                    r.result = out[i]
+                    r.result = out[i] if self.keep_results else None
                 self.free.append(si)
                 done.append(b)
             else:

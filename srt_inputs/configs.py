@@ -92,25 +92,25 @@ def cylinder_aperture(name: str, m: int, half_width: float, radius: float,
                     zpos=zpos, radii=radii)
 
 
-CONFIG_NAMES = ("cfg1", "cfg2", "cfg3", "cfg5_64", "cfg5_128", "cfg5_192")
+CONFIG_NAMES = ("grid32", "grid128", "pact256", "serve64", "serve128", "serve192")
 
 
 def config(name: str) -> Aperture:
     """The named workload geometries.
 
-    cfg1      32^3 on [-1,1]^3, R=1.5, 16 angles x 16 heights x 64 radii, l_max=3.5
-    cfg2      128^3 on [-1,1]^3, R=1.3, 128 x 128 x 512
-    cfg3      256^3 at 0.1 mm (W=12.8 mm), R=1.2 W, 512 x 256 x 1024 (PACT scale)
-    cfg5_N    N^3 on [-1,1]^3, R=1.3, N x N x 4N (serving mix, N in 64/128/192)
+    grid32    32^3 on [-1,1]^3, R=1.5, 16 angles x 16 heights x 64 radii, l_max=3.5
+    grid128   128^3 on [-1,1]^3, R=1.3, 128 x 128 x 512
+    pact256   256^3 at 0.1 mm (W=12.8 mm), R=1.2 W, 512 x 256 x 1024 (PACT scale)
+    serveN    N^3 on [-1,1]^3, R=1.3, N x N x 4N (serving mix, N in 64/128/192)
     """
-    if name == "cfg1":
-        return cylinder_aperture("cfg1", 32, 1.0, 1.5, 16, 16, 64, l_max=3.5)
-    if name == "cfg2":
-        return cylinder_aperture("cfg2", 128, 1.0, 1.3, 128, 128, 512)
-    if name == "cfg3":
+    if name == "grid32":
+        return cylinder_aperture("grid32", 32, 1.0, 1.5, 16, 16, 64, l_max=3.5)
+    if name == "grid128":
+        return cylinder_aperture("grid128", 128, 1.0, 1.3, 128, 128, 512)
+    if name == "pact256":
         w = 12.8
-        return cylinder_aperture("cfg3", 256, w, 1.2 * w, 512, 256, 1024)
-    if name.startswith("cfg5_"):
-        n = int(name.split("_")[1])
+        return cylinder_aperture("pact256", 256, w, 1.2 * w, 512, 256, 1024)
+    if name.startswith("serve"):
+        n = int(name[len("serve"):])
         return cylinder_aperture(name, n, 1.0, 1.3, n, n, 4 * n)
     raise KeyError(name)

@@ -134,16 +134,21 @@ def cylinder_phantom(ap: Aperture, rng: np.random.Generator, n: int = 200,
     return vol
 
 
-def phantom(ap: Aperture, cfg: int) -> np.ndarray:
-    """The seeded phantom of a workload (float64, [z][y][x])."""
-    if cfg == 1:
+def phantom(ap: Aperture) -> np.ndarray:
+    """The seeded phantom of a named workload (float64, [z][y][x]): three
+    balls on the 32^3 grid, ellipsoids plus noise on the 128^3 grid and the
+    serving grids, thin cylinders at PACT scale."""
+    if ap.name == "grid32":
         return voxelize_balls(ap, balls_params(np.random.default_rng(1001)))
-    if cfg in (2, 5):
-        return ellipsoid_phantom(ap, np.random.default_rng(1000 + cfg),
-                                 noise_rng=np.random.default_rng(2000 + cfg))
-    if cfg == 3:
+    if ap.name == "grid128":
+        return ellipsoid_phantom(ap, np.random.default_rng(1002),
+                                 noise_rng=np.random.default_rng(2002))
+    if ap.name.startswith("serve"):
+        return ellipsoid_phantom(ap, np.random.default_rng(1005),
+                                 noise_rng=np.random.default_rng(2005))
+    if ap.name == "pact256":
         return cylinder_phantom(ap, np.random.default_rng(1003))
-    raise KeyError(cfg)
+    raise KeyError(ap.name)
 
 
 def batch_phantoms(ap: Aperture, n: int, seed0: int = 4000) -> np.ndarray:

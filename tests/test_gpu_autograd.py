@@ -24,7 +24,7 @@ def setup():
     if not torch.cuda.is_available():
         pytest.fail("GPU tests need a ROCm device")
     from paper_2402_15641_amd import SRTPlan
-    ap, a12s, a34 = operators("cfg2")
+    ap, a12s, a34 = operators("grid128")
     plan = SRTPlan.from_geometry(ap, value_dtype="f32")
     f_true = torch.from_numpy(phantoms.batch_phantoms(ap, 8)).float().cuda()
     y = plan.forward(f_true)

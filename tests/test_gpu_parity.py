@@ -42,10 +42,10 @@ def _np(t):
 
 
 # ------------------------------------------------------------------ operators
-def test_operators_match_oracle_cfg1():
+def test_operators_match_oracle_grid32():
     """Every stored weight equals the oracle's arc length (FP64 plan), the
     transposes hold the same entries, and dropped rho cells are empty."""
-    ap, a12s, a34 = operators("cfg1")
+    ap, a12s, a34 = operators("grid32")
     plan = _plan(ap, "f64")
     h = ap.dxy
     r, c, v = plan.export_coo(0)
@@ -69,7 +69,7 @@ def test_operators_match_oracle_cfg1():
 @pytest.mark.parametrize("weight", ["bf16", "f16"])
 def test_rounded_weights_are_nearest(weight):
     """16-bit weights are the FP64 arc lengths rounded once to nearest."""
-    ap, a12s, a34 = operators("cfg1")
+    ap, a12s, a34 = operators("grid32")
     plan = _plan(ap, "f32", weight)
     r, c, v = plan.export_coo(1)
     B = sp.csr_matrix((v, (r, c)), shape=(ap.n_z * ap.n_radii, plan.info["live_radii"] * ap.mz))
@@ -82,11 +82,11 @@ def test_rounded_weights_are_nearest(weight):
     assert np.all(diff.data <= ulp * refv + tiny)
 
 
-# ------------------------------------------------------------------ cfg1
+# ------------------------------------------------------------------ grid32
 @pytest.mark.parametrize("value,tol", [("f64", 1e-12), ("f32", 1e-5)])
-def test_cfg1_forward_adjoint(value, tol):
-    ap, a12s, a34 = operators("cfg1")
-    F = phantoms.phantom(ap, 1)
+def test_grid32_forward_adjoint(value, tol):
+    ap, a12s, a34 = operators("grid32")
+    F = phantoms.phantom(ap)
     g = phantoms.gaussian_data(ap, np.random.default_rng(2001))
     dt = torch.float64 if value == "f64" else torch.float32
     Ft, gt = _t(F, dt), _t(g, dt)
@@ -134,7 +134,7 @@ def test_no_sphere_reaches_the_grid():
 
 
 def test_batch_and_workspace_are_bitwise_stable():
-    ap, a12s, a34 = operators("cfg1")
+    ap, a12s, a34 = operators("grid32")
     plan = _plan(ap, "f32")
     rng = np.random.default_rng(9)
     vols = _t(rng.uniform(0, 1, (3,) + ap.vol_shape), torch.float32)
@@ -151,11 +151,11 @@ def test_batch_and_workspace_are_bitwise_stable():
     assert e.value.status == SRT_EINVAL
 
 
-# ------------------------------------------------------------------ cfg2
+# ------------------------------------------------------------------ grid128
 @pytest.fixture(scope="module")
-def cfg2():
-    ap, a12s, a34 = operators("cfg2")
-    F = phantoms.phantom(ap, 2)
+def grid128():
+    ap, a12s, a34 = operators("grid128")
+    F = phantoms.phantom(ap)
     Ft = _t(F, torch.float32)
     Fin = _np(Ft)[None]
     Y = oracle_forward(ap, a12s, a34, Fin)
@@ -165,8 +165,8 @@ def cfg2():
     return ap, Ft, gt, Y, Fp
 
 
-def test_cfg2_forward_adjoint_f32(cfg2):
-    ap, Ft, gt, Y, Fp = cfg2
+def test_grid128_forward_adjoint_f32(grid128):
+    ap, Ft, gt, Y, Fp = grid128
     plan = _plan(ap, "f32")
     Yg = plan.forward(Ft[None].contiguous())
     assert rel_l2(_np(Yg), Y) <= 1e-5
@@ -179,8 +179,8 @@ def test_cfg2_forward_adjoint_f32(cfg2):
 
 
 @pytest.mark.parametrize("weight", ["bf16", "f16"])
-def test_cfg2_rounded_weights(cfg2, weight):
-    ap, Ft, gt, Y, Fp = cfg2
+def test_grid128_rounded_weights(grid128, weight):
+    ap, Ft, gt, Y, Fp = grid128
     plan = _plan(ap, "f32", weight)
     Yg = plan.forward(Ft[None].contiguous())
     Fg = plan.adjoint(gt)
@@ -191,14 +191,14 @@ def test_cfg2_rounded_weights(cfg2, weight):
     assert abs(lhs - rhs) / (float(Yg.double().norm()) * float(gt.double().norm())) <= 1e-6
 
 
-# ------------------------------------------------------------------ cfg3 (full size)
-def test_cfg3_sampled_forward_and_sparse_adjoint():
+# ------------------------------------------------------------------ pact256 (full size)
+def test_pact256_sampled_forward_and_sparse_adjoint():
     """At the 256^3 PACT-scale workload, in the launch configuration the
     benchmark times: forward outputs of sampled (column, height) pairs against
     the oracle, and the full adjoint volume of data that is non-zero on a few
     columns and heights (the oracle needs only those rows)."""
-    ap = config("cfg3")
-    F = phantoms.phantom(ap, 3)
+    ap = config("pact256")
+    F = phantoms.phantom(ap)
     Ft = _t(F, torch.float32)
     Fin = _np(Ft)
     plan = _plan(ap, "f32")

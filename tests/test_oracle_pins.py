@@ -32,8 +32,8 @@ def _eval(expr):
 
 
 @pytest.fixture(scope="module")
-def cfg1():
-    ap = config("cfg1")
+def grid32():
+    ap = config("grid32")
     a12s, a34 = geo.assemble_all(ap)
     balls = phantoms.balls_params(np.random.default_rng(1001))
     F = phantoms.voxelize_balls(ap, balls)
@@ -153,10 +153,10 @@ def test_stage2_matches_disk_closed_form():
 
 
 # ------------------------------------------------------- P4: uniform balls
-def test_ball_cap_area_cfg1(cfg1):
+def test_ball_cap_area_grid32(grid32):
     """Composition of both stages against the exact SRT of three balls
     (spherical cap areas) at the 32^3 workload."""
-    ap, a12s, a34, balls, F = cfg1
+    ap, a12s, a34, balls, F = grid32
     Y = srt.forward(F, a12s, a34, ap.n_z, ap.n_radii)
     ex = cf.srt_of_balls(ap, balls)
     assert np.linalg.norm(Y - ex) / np.linalg.norm(ex) <= 6.5e-2
@@ -221,10 +221,10 @@ def test_distance_to_plain_srt_shrinks():
 
 
 # ------------------------------------------------------------ P7: mass
-def test_mass_invariant(cfg1):
+def test_mass_invariant(grid32):
     """Coarea: the sum over radii of dl * Y equals the mass of the volume for
     every sensor, up to the midpoint rule in l."""
-    ap, a12s, a34, balls, F = cfg1
+    ap, a12s, a34, balls, F = grid32
     Y = srt.forward(F, a12s, a34, ap.n_z, ap.n_radii)
     dl = ap.radii[1] - ap.radii[0]
     rel = np.abs(Y.sum(-1) * dl / (F.sum() * ap.dxy ** 2 * ap.dz) - 1)
@@ -242,9 +242,9 @@ def test_mass_invariant_refines():
 
 
 # ------------------------------------------------------------ P8: adjoint
-def test_dot_product(cfg1):
+def test_dot_product(grid32):
     """<A f, g> = <f, A^T g> for the aperture-summed Alg. 2."""
-    ap, a12s, a34, balls, F = cfg1
+    ap, a12s, a34, balls, F = grid32
     g = np.random.default_rng(2001).standard_normal(ap.data_shape)
     Y = srt.forward(F, a12s, a34, ap.n_z, ap.n_radii)
     Fp = srt.adjoint(g, a12s, a34, ap.ms, ap.mz)
@@ -252,10 +252,10 @@ def test_dot_product(cfg1):
     assert rel <= 1e-13
 
 
-def test_adjoint_is_explicit_transpose(cfg1):
+def test_adjoint_is_explicit_transpose(grid32):
     """Alg. 2 applied to unit data vectors reproduces the rows of the forward
     operator (explicit transpose on a few entries)."""
-    ap, a12s, a34, balls, F = cfg1
+    ap, a12s, a34, balls, F = grid32
     rng = np.random.default_rng(3)
     for _ in range(5):
         a, h, l = rng.integers(ap.n_angles), rng.integers(ap.n_z), rng.integers(20, ap.n_radii)
@@ -267,11 +267,11 @@ def test_adjoint_is_explicit_transpose(cfg1):
 
 
 # ------------------------------------------------------------ P9: symmetries
-def test_symmetries(cfg1):
+def test_symmetries(grid32):
     """Rotating the object 90 deg about z shifts the sensor angle by N_a/4;
     mirroring y maps angle a to -a; flipping z reverses the sensor heights;
     A34 does not depend on the sensor column."""
-    ap, a12s, a34, balls, _ = cfg1
+    ap, a12s, a34, balls, _ = grid32
     F = np.random.default_rng(7).uniform(0, 1, ap.vol_shape)
     M = ap.ms
     Y = srt.forward(F, a12s, a34, ap.n_z, ap.n_radii)
@@ -288,8 +288,8 @@ def test_symmetries(cfg1):
 
 
 # ------------------------------------------------------------ P10: sanity
-def test_linearity_and_sign(cfg1):
-    ap, a12s, a34, balls, F = cfg1
+def test_linearity_and_sign(grid32):
+    ap, a12s, a34, balls, F = grid32
     rng = np.random.default_rng(11)
     F2 = rng.uniform(0, 1, ap.vol_shape)
     Y1 = srt.forward(F, a12s, a34, ap.n_z, ap.n_radii)
