@@ -4,9 +4,11 @@
 // does not depend on the dense index: A12_a is shared by every z-slice and
 // batch item, A34 by every column angle and batch item (Sec. 2: sensors of a
 // column share the first transform; all columns share the second). The dense
-// index therefore runs across the lanes of a wavefront, the weight and the
-// column index of a nonzero are wave-uniform (scalar loads), and every
-// nonzero costs one coalesced row read plus one FMA per lane.
+// index therefore runs across the lanes of a lane group: a nonzero's column
+// and weight are the same for all of the group's lanes, and every nonzero
+// costs one contiguous read of a staged dense row plus one FMA per lane and
+// dense value. Rows of the operator are grouped into blocks whose dense rows
+// are staged once in LDS for all of the block's rows (see tiled.hip).
 //
 // Layouts between the stages (row index first, dense index last):
 //   Ft [p][b][k]          pixel-major volume      (Alg. 1 reshape to M_s^2 x M_z)
@@ -36,17 +38,12 @@ template <typename T> struct Vec16;
 template <> struct Vec16<float> { using type = float4; };
 template <> struct Vec16<double> { using type = double2; };
 
-// An operator entry as staged in LDS: local column and weight.
-template <typename T> struct LdsEnt {
-  int32_t col;
-  T w;
-};
-
 // Tile geometry shared by the kernel and its launcher. A wavefront is
-// GROUPS lane groups of LPG lanes; a group works on one row at a time and its
-// lanes split the dense slice: lane li holds NV vectors of VS values, vector m
-// at slice offset (m * LPG + li) * VS. One vector load of a group therefore
-// covers LPG * 16 = 256 contiguous bytes, i.e. every LDS bank once.
+// GROUPS lane groups of LPG lanes; a group works on one quad of rows at a
+// time and its lanes split the dense slice: lane li holds NV vectors of VS
+// values, vector m at slice offset (m * LPG + li) * VS. One vector load of a
+// group therefore covers LPG * 16 = 256 contiguous bytes, i.e. every LDS bank
+// once.
 template <typename T> struct TileShape {
   static constexpr int VS = 16 / sizeof(T);      // values per 16-byte vector
   static constexpr int LPG = 16;                 // lanes per group
@@ -55,32 +52,102 @@ template <typename T> struct TileShape {
   static constexpr int DW = LPG * NV * VS;       // dense values per slice
   static constexpr int PIECES = DW / VS;         // 16-byte pieces per staged dense row
   static_assert(kNW * GROUPS == kNQ, "one quad per lane group");
+  static_assert(PIECES == 32, "a staged dense row is half a wavefront of 16-byte pieces");
   static constexpr int NT = kNW * 64;            // threads per workgroup
   static constexpr int E = sizeof(T) == 4 ? kE32 : kE64;  // entries per chunk
-  static constexpr int DENSE_PER_T = kC * PIECES / NT;
-  static constexpr int ENT_PER_T = (E + NT - 1) / NT;
+  static constexpr int PAIRS_PER_WAVE = kC / 2 / kNW;     // dense row pairs a wave stages
+  static_assert(kC % (2 * kNW) == 0, "dense rows split evenly over the wavefronts");
 };
 
-// One chunk's staged data while it travels from memory to LDS.
-template <typename T, typename WT> struct InFlight {
-  typename Vec16<T>::type dv[TileShape<T>::DENSE_PER_T];
-  int32_t ec[TileShape<T>::ENT_PER_T];
-  WT ew[TileShape<T>::ENT_PER_T];
-  int32_t sv;
+// The hardware deals workgroups round-robin to the 8 XCDs (id % 8), each
+// with its own L2. Renumbering so that XCD x gets a contiguous range of the
+// (slice-major) work order makes the blocks that run side by side on one XCD
+// neighbours in the operator, which share dense rows through that L2.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_local(int id, int n) {
+  const int x = id % kXcds, k = id / kXcds;
+  const int q = n / kXcds, r = n % kXcds;
+  return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(1))) const void gbl_void_t;
+
+// Asynchronous copies straight from global memory into LDS, 16 or 4 bytes
+// per lane: lane l writes dst + l * size, where dst is the same for the
+// whole wavefront. Lanes that are switched off write nothing. Completion is
+// counted like any other vector load (vmcnt).
+__device__ __forceinline__ void lds_dma16(const void *src, void *dst) {
+  __builtin_amdgcn_global_load_lds((gbl_void_t *)src, (lds_void_t *)dst, 16, 0, 0);
+}
+__device__ __forceinline__ void lds_dma4(const void *src, void *dst) {
+  __builtin_amdgcn_global_load_lds((gbl_void_t *)src, (lds_void_t *)dst, 4, 0, 0);
+}
+
+// Waits until every vector memory operation of this wavefront (loads and
+// LDS copies) has completed: vmcnt(0), other counters untouched.
+__device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+// Four consecutive weights from LDS (stored format) as accumulation type.
+template <typename T, typename WT> struct Quad4;
+template <> struct Quad4<float, float> {
+  static __device__ __forceinline__ void load(const uint32_t *raw, int e, float w[4]) {
+    const float4 v = *reinterpret_cast<const float4 *>(raw + e);
+    w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
+  }
+};
+template <> struct Quad4<float, uint16_t> {  // bfloat16: the upper half of an f32
+  static __device__ __forceinline__ void load(const uint32_t *raw, int e, float w[4]) {
+    const uint2 v = *reinterpret_cast<const uint2 *>(raw + e / 2);
+    w[0] = __uint_as_float(v.x << 16); w[1] = __uint_as_float(v.x & 0xffff0000u);
+    w[2] = __uint_as_float(v.y << 16); w[3] = __uint_as_float(v.y & 0xffff0000u);
+  }
+};
+template <> struct Quad4<float, _Float16> {
+  static __device__ __forceinline__ void load(const uint32_t *raw, int e, float w[4]) {
+    const _Float16 *h = reinterpret_cast<const _Float16 *>(raw) + e;
+    typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+    const h4 v = *reinterpret_cast<const h4 *>(h);
+    w[0] = (float)v.x; w[1] = (float)v.y; w[2] = (float)v.z; w[3] = (float)v.w;
+  }
+};
+template <> struct Quad4<double, double> {
+  static __device__ __forceinline__ void load(const uint32_t *raw, int e, double w[4]) {
+    const double2 a = *reinterpret_cast<const double2 *>(raw + 2 * e);
+    const double2 b = *reinterpret_cast<const double2 *>(raw + 2 * e + 4);
+    w[0] = a.x; w[1] = a.y; w[2] = b.x; w[3] = b.y;
+  }
 };
 
-// One workgroup (one per CU) = one row block x one slice of the dense
-// index; slices are outermost in the grid so the current slice of the dense
-// operand stays in the last-level cache while every block streams through it.
+// One chunk's worth of LDS: staged dense rows (row kC stays zero and is what
+// padding entries point at), the entries' local columns and weights (as
+// stored), and the quads' entry offsets.
+template <typename T, typename WT> struct ChunkLds {
+  using V16 = typename Vec16<T>::type;
+  static constexpr int E = TileShape<T>::E;
+  static constexpr int WWORDS = E * (int)sizeof(WT) / 4;
+  V16 *dense;
+  int32_t *col;
+  uint32_t *w;
+  int32_t *seg;
+};
+
+// One workgroup (one per CU) = one row block x one slice of the dense index.
 //
-// Chunks are double-buffered in LDS: while the wavefronts consume chunk c
-// from one buffer, the loads of chunk c+1 (its dense rows, entries and
-// per-row offsets) are in flight into registers and land in the other buffer
-// afterwards; the columns of chunk c+2 are fetched one step earlier still.
+// Chunks are double-buffered in LDS. While the wavefronts consume chunk c
+// from one buffer, chunk c+1 (its dense rows, entries and quad offsets) is
+// copied from memory straight into the other buffer by LDS DMA, each
+// wavefront issuing its share and waiting for it only at the end of chunk c;
+// the column list of chunk c+2 is fetched one step earlier still. The two
+// buffers are separate LDS arrays and the chunk loop is unrolled by two, so
+// the compiler sees that the copies in flight never alias the buffer being
+// read.
+//
 // A wavefront is GROUPS lane groups (see TileShape); each group runs one
 // quad (kQ rows) in lockstep: per step it reads kQ entries (one per quad row,
 // padded so the rows advance together), kQ * NV dense vectors and does
-// kQ * NV * VS fused multiply-adds per lane.
+// kQ * NV * VS fused multiply-adds per lane. The next step's entries are read
+// before this step's products, so their LDS latency overlaps the dense reads.
 template <typename T, typename WT, bool VEC>
 __device__ __forceinline__ void tiled_body(const int32_t *__restrict__ blk_rows,
                                            const int32_t *__restrict__ blk_chunk,
@@ -90,27 +157,25 @@ __device__ __forceinline__ void tiled_body(const int32_t *__restrict__ blk_rows,
                                            const int32_t *__restrict__ qseg,
                                            const int32_t *__restrict__ ent_col,
                                            const WT *__restrict__ ent_w, const T *__restrict__ X,
-                                           T *__restrict__ Y, int nblk, int D, T scale) {
+                                           T *__restrict__ Y, int nblk, int D, T scale,
+                                           int remap) {
   using S = TileShape<T>;
   using V16 = typename Vec16<T>::type;
+  using L = ChunkLds<T, WT>;
   constexpr int VS = S::VS, NV = S::NV, DW = S::DW, PIECES = S::PIECES;
-  constexpr int LPG = S::LPG, GROUPS = S::GROUPS;
-  constexpr int NT = S::NT, DPT = S::DENSE_PER_T, EPT = S::ENT_PER_T, E = S::E;
-  __shared__ V16 lds_dense[2][(kC + 1) * PIECES];  // column kC stays zero (padding)
-  __shared__ LdsEnt<T> lds_ent[2][E];
-  __shared__ int32_t lds_seg[2][kNQ + 1];
+  constexpr int LPG = S::LPG, GROUPS = S::GROUPS, E = S::E, PPW = S::PAIRS_PER_WAVE;
+  __shared__ V16 dense0[(kC + 1) * PIECES], dense1[(kC + 1) * PIECES];
+  __shared__ int32_t col0[E], col1[E];
+  __shared__ uint32_t w0[L::WWORDS], w1[L::WWORDS];
+  __shared__ int32_t seg0[kNQ + 1], seg1[kNQ + 1];
+  const L buf0{dense0, col0, w0, seg0}, buf1{dense1, col1, w1, seg1};
 
-  const int bid = blockIdx.x;
+  const int bid = remap ? xcd_local(blockIdx.x, gridDim.x) : (int)blockIdx.x;
   const int blk = bid % nblk, slice = bid / nblk;
   const int d0 = slice * DW;
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lane = tid & 63, grp = lane / LPG, li = lane % LPG;
-  const int q = tid % PIECES;            // piece within a dense row
-  const int d_piece = d0 + q * VS;
-  // VEC: the dense width D is a multiple of VS, so rows are read and written
-  // in whole 16-byte vectors (otherwise element by element).
-  constexpr bool vec_ok = VEC;
 
   V16 acc[kQ][NV];
 #pragma unroll
@@ -118,107 +183,122 @@ __device__ __forceinline__ void tiled_body(const int32_t *__restrict__ blk_rows,
 #pragma unroll
     for (int m = 0; m < NV; ++m) acc[j][m] = V16{};
   if (tid < PIECES) {
-    lds_dense[0][kC * PIECES + tid] = V16{};
-    lds_dense[1][kC * PIECES + tid] = V16{};
+    dense0[kC * PIECES + tid] = V16{};
+    dense1[kC * PIECES + tid] = V16{};
   }
 
   const int c0 = blk_chunk[blk], c1 = blk_chunk[blk + 1];
 
-  // Column of the dense row behind this thread's k-th piece of chunk c.
+  // Dense row staged by this lane's k-th copy: rows come in pairs, one per
+  // half wavefront, each half copying the row's PIECES 16-byte pieces.
+  const int half = lane >> 5, piece = lane & 31;
   auto load_cols = [&](int c, int32_t *cols) {
 #pragma unroll
-    for (int k = 0; k < DPT; ++k) cols[k] = chunk_cols[(size_t)c * kC + (tid + k * NT) / PIECES];
+    for (int k = 0; k < PPW; ++k)
+      cols[k] = chunk_cols[(size_t)c * kC + 2 * (wave + kNW * k) + half];
   };
-  auto issue = [&](int c, const int32_t *cols, InFlight<T, WT> &st) {
+  // Issues this wavefront's share of the copies of chunk c into buffer b.
+  auto stage = [&](int c, const L &b, const int32_t *cols) {
     const int n = chunk_ncols[c];
     const int ce0 = chunk_ent[c], ne = chunk_ent[c + 1] - ce0;
+    if constexpr (VEC) {
+      const int d = d0 + piece * VS;
 #pragma unroll
-    for (int k = 0; k < DPT; ++k) {
-      const int u = (tid + k * NT) / PIECES;
-      st.dv[k] = V16{};
-      if (u < n) {
-        const T *src = X + (size_t)cols[k] * D + d_piece;
-        if constexpr (VEC) {
-          if (d_piece < D) st.dv[k] = *reinterpret_cast<const V16 *>(src);
-        } else {
-          T *dd = reinterpret_cast<T *>(&st.dv[k]);
-#pragma unroll
-          for (int v = 0; v < VS; ++v)
-            if (d_piece + v < D) dd[v] = src[v];
-        }
+      for (int k = 0; k < PPW; ++k) {
+        const int p = wave + kNW * k;
+        if (2 * p + half < n && d < D) lds_dma16(X + (size_t)cols[k] * D + d, b.dense + 2 * p * PIECES);
+      }
+    } else {
+      // D is not a multiple of VS: copy 4-byte words of each row's slice;
+      // a row's slice is 2 * 64 words, one wavefront copy per half.
+      constexpr int WPV = 16 / 4;  // words per 16-byte piece
+      for (int i = wave; i < 2 * kC; i += kNW) {
+        const int u = i >> 1;
+        if (u >= n) break;
+        const int col = chunk_cols[(size_t)c * kC + u];
+        const int word = (i & 1) * 64 + lane;           // word within the row's slice
+        const int elem = d0 + word * 4 / (int)sizeof(T);  // first value it holds
+        if (elem < D)
+          lds_dma4(reinterpret_cast<const uint32_t *>(X + (size_t)col * D + d0) + word,
+                     b.dense + u * PIECES + (i & 1) * (64 / WPV));
       }
     }
-#pragma unroll
-    for (int k = 0; k < EPT; ++k) {
-      const int i = tid + k * NT;
-      st.ec[k] = 0;
-      st.ew[k] = WT{};
-      if (i < ne) {
-        st.ec[k] = ent_col[ce0 + i];
-        st.ew[k] = ent_w[ce0 + i];
-      }
+    for (int j = wave; j * 64 < ne; j += kNW) {
+      const int i = j * 64 + lane;
+      if (i < ne) lds_dma4(ent_col + ce0 + i, b.col + j * 64);
     }
-    st.sv = tid <= kNQ ? qseg[(size_t)c * (kNQ + 1) + tid] : 0;
+    const int nw = ne * (int)sizeof(WT) / 4;
+    const uint32_t *wsrc = reinterpret_cast<const uint32_t *>(ent_w + ce0);
+    for (int j = wave; j * 64 < nw; j += kNW) {
+      const int i = j * 64 + lane;
+      if (i < nw) lds_dma4(wsrc + i, b.w + j * 64);
+    }
+    for (int j = wave; j * 64 < kNQ + 1; j += kNW) {
+      const int i = j * 64 + lane;
+      if (i < kNQ + 1) lds_dma4(qseg + (size_t)c * (kNQ + 1) + i, b.seg + j * 64);
+    }
   };
-  auto commit = [&](int buf, const InFlight<T, WT> &st) {
+  // This lane group's quad over one staged chunk.
+  auto consume = [&](const L &b) {
+    const int q = wave * GROUPS + grp;
+    const int e0 = b.seg[q], e1 = b.seg[q + 1];
+    const int ef = min(e0, E - kQ);  // a quad may start at the chunk's very end
+    int4 cn = *reinterpret_cast<const int4 *>(b.col + ef);
+    T wn[kQ];
+    Quad4<T, WT>::load(b.w, ef, wn);
+    // Keep the loop's own entry reads where they are written (a step ahead):
+    // without this the compiler merges them with these first reads into one
+    // read at the top of the loop, which stalls every step on it.
+    asm volatile("" : "+v"(cn.x), "+v"(cn.y), "+v"(cn.z), "+v"(cn.w));
+    for (int e = e0; e < e1; e += kQ) {
+      const int cj[kQ] = {cn.x, cn.y, cn.z, cn.w};
+      T ww[kQ];
 #pragma unroll
-    for (int k = 0; k < DPT; ++k) lds_dense[buf][tid + k * NT] = st.dv[k];
+      for (int j = 0; j < kQ; ++j) ww[j] = wn[j];
+      V16 x[kQ][NV];
 #pragma unroll
-    for (int k = 0; k < EPT; ++k) {
-      const int i = tid + k * NT;
-      if (i < E) lds_ent[buf][i] = LdsEnt<T>{st.ec[k] * PIECES, to_acc<T, WT>(st.ew[k])};
+      for (int j = 0; j < kQ; ++j)
+#pragma unroll
+        for (int m = 0; m < NV; ++m) x[j][m] = b.dense[cj[j] * PIECES + li + m * LPG];
+      // next step's entries, read while this step's rows are in flight
+      // (clamped: the read after the last step is unused)
+      const int en = min(e + kQ, E - kQ);
+      cn = *reinterpret_cast<const int4 *>(b.col + en);
+      Quad4<T, WT>::load(b.w, en, wn);
+#pragma unroll
+      for (int j = 0; j < kQ; ++j)
+#pragma unroll
+        for (int m = 0; m < NV; ++m) {
+          const T *xs = reinterpret_cast<const T *>(&x[j][m]);
+          T *as = reinterpret_cast<T *>(&acc[j][m]);
+#pragma unroll
+          for (int v = 0; v < VS; ++v) as[v] = fma(ww[j], xs[v], as[v]);
+        }
     }
-    if (tid <= kNQ) lds_seg[buf][tid] = st.sv;
   };
 
   if (c0 < c1) {
-    int32_t cols_next[DPT], cols_after[DPT];
-    InFlight<T, WT> st;
-    load_cols(c0, cols_next);
-    issue(c0, cols_next, st);
-    if (c0 + 1 < c1) load_cols(c0 + 1, cols_next);
-    commit(0, st);
+    int32_t cols_a[PPW], cols_b[PPW];
+    if constexpr (VEC) load_cols(c0, cols_a);
+    stage(c0, buf0, cols_a);
+    if (VEC && c0 + 1 < c1) load_cols(c0 + 1, cols_b);
+    wait_vmem();
     __syncthreads();
-    for (int c = c0; c < c1; ++c) {
-      // Keep each chunk's loads inside its own iteration: if the compiler
-      // rotates some of them behind the barrier, the loop head waits for them.
-      asm volatile("" ::: "memory");
-      const int cur = (c - c0) & 1;
-      const bool more = c + 1 < c1;
-      if (more) {
-        issue(c + 1, cols_next, st);
-        if (c + 2 < c1) load_cols(c + 2, cols_after);
+    // one chunk: copy the next into `nxt`, consume `cur`, wait, publish
+    auto step = [&](int c, const L &cur, const L &nxt, const int32_t *cols_next,
+                    int32_t *cols_after) {
+      if (c + 1 < c1) {
+        stage(c + 1, nxt, cols_next);
+        if (VEC && c + 2 < c1) load_cols(c + 2, cols_after);
       }
-      // ---- consume chunk c: this lane group's quad, kQ rows in lockstep
-      {
-        const int q = wave * GROUPS + grp;
-        const int e0 = lds_seg[cur][q], e1 = lds_seg[cur][q + 1];
-        for (int e = e0; e < e1; e += kQ) {
-          LdsEnt<T> en[kQ];
-#pragma unroll
-          for (int j = 0; j < kQ; ++j) en[j] = lds_ent[cur][e + j];
-          V16 x[kQ][NV];
-#pragma unroll
-          for (int j = 0; j < kQ; ++j)
-#pragma unroll
-            for (int m = 0; m < NV; ++m) x[j][m] = lds_dense[cur][en[j].col + li + m * LPG];
-#pragma unroll
-          for (int j = 0; j < kQ; ++j)
-#pragma unroll
-            for (int m = 0; m < NV; ++m) {
-              const T *xs = reinterpret_cast<const T *>(&x[j][m]);
-              T *as = reinterpret_cast<T *>(&acc[j][m]);
-#pragma unroll
-              for (int v = 0; v < VS; ++v) as[v] = fma(en[j].w, xs[v], as[v]);
-            }
-        }
-      }
-      if (more) {
-        commit(cur ^ 1, st);
-#pragma unroll
-        for (int k = 0; k < DPT; ++k) cols_next[k] = cols_after[k];
-      }
+      consume(cur);
+      wait_vmem();
       __syncthreads();
+    };
+    for (int c = c0; c < c1; c += 2) {
+      step(c, buf0, buf1, cols_b, cols_a);
+      if (c + 1 >= c1) break;
+      step(c + 1, buf1, buf0, cols_a, cols_b);
     }
   }
   // ---- write: each row once
@@ -257,9 +337,9 @@ __device__ __forceinline__ void tiled_body(const int32_t *__restrict__ blk_rows,
       const int32_t *__restrict__ chunk_cols, const int32_t *__restrict__ chunk_ncols,         \
       const int32_t *__restrict__ chunk_ent, const int32_t *__restrict__ qseg,                 \
       const int32_t *__restrict__ ent_col, const WT *__restrict__ ent_w,                       \
-      const T *__restrict__ X, T *__restrict__ Y, int nblk, int D, T scale) {                  \
+      const T *__restrict__ X, T *__restrict__ Y, int nblk, int D, T scale, int remap) {       \
     tiled_body<T, WT, VEC>(blk_rows, blk_chunk, chunk_cols, chunk_ncols, chunk_ent, qseg,      \
-                           ent_col, ent_w, X, Y, nblk, D, scale);                              \
+                           ent_col, ent_w, X, Y, nblk, D, scale, remap);                       \
   }
 SRT_STAGE_KERNEL(stage1_fwd)  // A12_a applied to every slice: G = A12 F
 SRT_STAGE_KERNEL(stage2_fwd)  // A34 applied to every column: Y = A34 G
@@ -325,10 +405,14 @@ Status spmm(Stage st, const Tiled &m, const T *X, T *Y, int D, hipStream_t s) {
   if (grid > INT32_MAX) return fail(SRT_ENOTSUP, "launch grid too large");
   const T scale = (T)(1.0 / m.scale);
   const WT *w = (const WT *)m.ent_w;
+  // XCD-local work order: measured to cut L2 misses for both forward stages
+  // and the stage-1 adjoint; the stage-2 adjoint's blocks share more when
+  // dealt round-robin.
+  const int remap = st != Stage::s2_adj;
   auto go = [&](auto kern) {
     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kNW * 64), 0, s, m.blk_rows, m.blk_chunk,
                        m.chunk_cols, m.chunk_ncols, m.chunk_ent, m.qseg, m.ent_col, w, X, Y,
-                       (int)m.nblk, D, scale);
+                       (int)m.nblk, D, scale, remap);
   };
   const bool vec = D % TileShape<T>::VS == 0;
   switch (st) {

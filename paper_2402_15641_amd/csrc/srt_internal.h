@@ -97,7 +97,7 @@ constexpr int kNW = 16;    // wavefronts per workgroup
 struct RowGrid {
   int64_t n1 = 0, n2 = 0;
   int64_t b1 = 0, b2 = 0;
-  bool along_i1 = false;
+  bool along_i1 = false;  // consecutive block slots step along i1 (else along i2)
 };
 
 struct Tiled {
