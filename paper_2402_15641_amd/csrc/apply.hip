@@ -84,6 +84,23 @@ __device__ __forceinline__ void lds_dma4(const void *src, void *dst) {
   __builtin_amdgcn_global_load_lds((gbl_void_t *)src, (lds_void_t *)dst, 4, 0, 0);
 }
 
+// The same copies through a buffer resource (base, byte size): a 32-bit
+// byte offset per lane, and reads past the end return zeros instead of
+// touching memory. While global_load_lds copies are in flight the compiler
+// waits for every outstanding LDS read at once (lgkmcnt(0)); with buffer
+// copies in flight it keeps waiting for the LDS reads one by one, which is
+// what lets the consume loop overlap its reads with its FMAs.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void *base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes,
+                                           0x00020000);
+}
+__device__ __forceinline__ void buf_dma16(__amdgpu_buffer_rsrc_t r, uint32_t off, void *dst) {
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_void_t *)dst, 16, (int)off, 0, 0, 0);
+}
+__device__ __forceinline__ void buf_dma4(__amdgpu_buffer_rsrc_t r, uint32_t off, void *dst) {
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_void_t *)dst, 4, (int)off, 0, 0, 0);
+}
+
 // Waits until every vector memory operation of this wavefront (loads and
 // LDS copies) has completed: vmcnt(0), other counters untouched.
 __device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
@@ -148,7 +165,11 @@ template <typename T, typename WT> struct ChunkLds {
 // padded so the rows advance together), kQ * NV dense vectors and does
 // kQ * NV * VS fused multiply-adds per lane. The next step's entries are read
 // before this step's products, so their LDS latency overlaps the dense reads.
-template <typename T, typename WT, bool VEC>
+// MODE 1: the dense width D is a multiple of VS and the dense operand spans
+// less than 4 GiB, so rows are staged in 16-byte pieces through buffer
+// copies. MODE 2: 16-byte pieces through global copies (operand of 4 GiB or
+// more). MODE 0: D is not a multiple of VS; rows are staged word by word.
+template <typename T, typename WT, int MODE>
 __device__ __forceinline__ void tiled_body(const int32_t *__restrict__ blk_rows,
                                            const int32_t *__restrict__ blk_chunk,
                                            const int32_t *__restrict__ chunk_cols,
@@ -158,7 +179,8 @@ __device__ __forceinline__ void tiled_body(const int32_t *__restrict__ blk_rows,
                                            const int32_t *__restrict__ ent_col,
                                            const WT *__restrict__ ent_w, const T *__restrict__ X,
                                            T *__restrict__ Y, int nblk, int D, T scale,
-                                           int remap) {
+                                           int remap, uint32_t xbytes) {
+  constexpr bool VEC = MODE != 0, BUF = MODE == 1;
   using S = TileShape<T>;
   using V16 = typename Vec16<T>::type;
   using L = ChunkLds<T, WT>;
@@ -203,10 +225,23 @@ __device__ __forceinline__ void tiled_body(const int32_t *__restrict__ blk_rows,
     const int ce0 = chunk_ent[c], ne = chunk_ent[c + 1] - ce0;
     if constexpr (VEC) {
       const int d = d0 + piece * VS;
+      if constexpr (BUF) {
+        // resource from the slice start to the operand's end
+        const auto r = buf_rsrc(X + d0, xbytes - (uint32_t)(d0 * sizeof(T)));
+        const uint32_t rowb = (uint32_t)D * sizeof(T);
 #pragma unroll
-      for (int k = 0; k < PPW; ++k) {
-        const int p = wave + kNW * k;
-        if (2 * p + half < n && d < D) lds_dma16(X + (size_t)cols[k] * D + d, b.dense + 2 * p * PIECES);
+        for (int k = 0; k < PPW; ++k) {
+          const int p = wave + kNW * k;
+          if (2 * p + half < n && d < D)
+            buf_dma16(r, (uint32_t)cols[k] * rowb + piece * 16u, b.dense + 2 * p * PIECES);
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < PPW; ++k) {
+          const int p = wave + kNW * k;
+          if (2 * p + half < n && d < D)
+            lds_dma16(X + (size_t)cols[k] * D + d, b.dense + 2 * p * PIECES);
+        }
       }
     } else {
       // D is not a multiple of VS: copy 4-byte words of each row's slice;
@@ -220,22 +255,40 @@ __device__ __forceinline__ void tiled_body(const int32_t *__restrict__ blk_rows,
         const int elem = d0 + word * 4 / (int)sizeof(T);  // first value it holds
         if (elem < D)
           lds_dma4(reinterpret_cast<const uint32_t *>(X + (size_t)col * D + d0) + word,
-                     b.dense + u * PIECES + (i & 1) * (64 / WPV));
+                   b.dense + u * PIECES + (i & 1) * (64 / WPV));
       }
     }
-    for (int j = wave; j * 64 < ne; j += kNW) {
-      const int i = j * 64 + lane;
-      if (i < ne) lds_dma4(ent_col + ce0 + i, b.col + j * 64);
-    }
     const int nw = ne * (int)sizeof(WT) / 4;
-    const uint32_t *wsrc = reinterpret_cast<const uint32_t *>(ent_w + ce0);
-    for (int j = wave; j * 64 < nw; j += kNW) {
-      const int i = j * 64 + lane;
-      if (i < nw) lds_dma4(wsrc + i, b.w + j * 64);
-    }
-    for (int j = wave; j * 64 < kNQ + 1; j += kNW) {
-      const int i = j * 64 + lane;
-      if (i < kNQ + 1) lds_dma4(qseg + (size_t)c * (kNQ + 1) + i, b.seg + j * 64);
+    if constexpr (BUF) {
+      const auto rc = buf_rsrc(ent_col + ce0, (uint32_t)ne * 4u);
+      for (int j = wave; j * 64 < ne; j += kNW) {
+        const int i = j * 64 + lane;
+        if (i < ne) buf_dma4(rc, (uint32_t)i * 4u, b.col + j * 64);
+      }
+      const auto rw = buf_rsrc(ent_w + ce0, (uint32_t)nw * 4u);
+      for (int j = wave; j * 64 < nw; j += kNW) {
+        const int i = j * 64 + lane;
+        if (i < nw) buf_dma4(rw, (uint32_t)i * 4u, b.w + j * 64);
+      }
+      const auto rq = buf_rsrc(qseg + (size_t)c * (kNQ + 1), (kNQ + 1) * 4u);
+      for (int j = wave; j * 64 < kNQ + 1; j += kNW) {
+        const int i = j * 64 + lane;
+        if (i < kNQ + 1) buf_dma4(rq, (uint32_t)i * 4u, b.seg + j * 64);
+      }
+    } else {
+      for (int j = wave; j * 64 < ne; j += kNW) {
+        const int i = j * 64 + lane;
+        if (i < ne) lds_dma4(ent_col + ce0 + i, b.col + j * 64);
+      }
+      const uint32_t *wsrc = reinterpret_cast<const uint32_t *>(ent_w + ce0);
+      for (int j = wave; j * 64 < nw; j += kNW) {
+        const int i = j * 64 + lane;
+        if (i < nw) lds_dma4(wsrc + i, b.w + j * 64);
+      }
+      for (int j = wave; j * 64 < kNQ + 1; j += kNW) {
+        const int i = j * 64 + lane;
+        if (i < kNQ + 1) lds_dma4(qseg + (size_t)c * (kNQ + 1) + i, b.seg + j * 64);
+      }
     }
   };
   // This lane group's quad over one staged chunk.
@@ -331,15 +384,16 @@ __device__ __forceinline__ void tiled_body(const int32_t *__restrict__ blk_rows,
 
 // One named kernel per stage so traces tell the stages apart.
 #define SRT_STAGE_KERNEL(NAME)                                                                 \
-  template <typename T, typename WT, bool VEC>                                                 \
-  __global__ __launch_bounds__(kNW * 64) void NAME(                                           \
+  template <typename T, typename WT, int MODE>                                                 \
+  __global__ __launch_bounds__(kNW * 64) __attribute__((amdgpu_waves_per_eu(4, 4))) void NAME(                                           \
       const int32_t *__restrict__ blk_rows, const int32_t *__restrict__ blk_chunk,             \
       const int32_t *__restrict__ chunk_cols, const int32_t *__restrict__ chunk_ncols,         \
       const int32_t *__restrict__ chunk_ent, const int32_t *__restrict__ qseg,                 \
       const int32_t *__restrict__ ent_col, const WT *__restrict__ ent_w,                       \
-      const T *__restrict__ X, T *__restrict__ Y, int nblk, int D, T scale, int remap) {       \
-    tiled_body<T, WT, VEC>(blk_rows, blk_chunk, chunk_cols, chunk_ncols, chunk_ent, qseg,      \
-                           ent_col, ent_w, X, Y, nblk, D, scale, remap);                       \
+      const T *__restrict__ X, T *__restrict__ Y, int nblk, int D, T scale, int remap,         \
+      uint32_t xbytes) {                                                                       \
+    tiled_body<T, WT, MODE>(blk_rows, blk_chunk, chunk_cols, chunk_ncols, chunk_ent, qseg,     \
+                            ent_col, ent_w, X, Y, nblk, D, scale, remap, xbytes);              \
   }
 SRT_STAGE_KERNEL(stage1_fwd)  // A12_a applied to every slice: G = A12 F
 SRT_STAGE_KERNEL(stage2_fwd)  // A34 applied to every column: Y = A34 G
@@ -409,18 +463,24 @@ Status spmm(Stage st, const Tiled &m, const T *X, T *Y, int D, hipStream_t s) {
   // and the stage-1 adjoint; the stage-2 adjoint's blocks share more when
   // dealt round-robin.
   const int remap = st != Stage::s2_adj;
+  // Buffer copies address the dense operand with 32-bit byte offsets.
+  const uint64_t xb = (uint64_t)m.ncols * (uint64_t)D * sizeof(T);
+  const int mode = D % TileShape<T>::VS != 0 ? 0 : (xb < (1ull << 32) ? 1 : 2);
+  const uint32_t xbytes = mode == 1 ? (uint32_t)xb : 0u;
   auto go = [&](auto kern) {
     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kNW * 64), 0, s, m.blk_rows, m.blk_chunk,
                        m.chunk_cols, m.chunk_ncols, m.chunk_ent, m.qseg, m.ent_col, w, X, Y,
-                       (int)m.nblk, D, scale, remap);
+                       (int)m.nblk, D, scale, remap, xbytes);
   };
-  const bool vec = D % TileShape<T>::VS == 0;
+#define SRT_GO(K)                                \
+  (mode == 1 ? go(K<T, WT, 1>) : mode == 2 ? go(K<T, WT, 2>) : go(K<T, WT, 0>))
   switch (st) {
-    case Stage::s1_fwd: vec ? go(stage1_fwd<T, WT, true>) : go(stage1_fwd<T, WT, false>); break;
-    case Stage::s2_fwd: vec ? go(stage2_fwd<T, WT, true>) : go(stage2_fwd<T, WT, false>); break;
-    case Stage::s2_adj: vec ? go(stage2_adj<T, WT, true>) : go(stage2_adj<T, WT, false>); break;
-    case Stage::s1_adj: vec ? go(stage1_adj<T, WT, true>) : go(stage1_adj<T, WT, false>); break;
+    case Stage::s1_fwd: SRT_GO(stage1_fwd); break;
+    case Stage::s2_fwd: SRT_GO(stage2_fwd); break;
+    case Stage::s2_adj: SRT_GO(stage2_adj); break;
+    case Stage::s1_adj: SRT_GO(stage1_adj); break;
   }
+#undef SRT_GO
   SRT_HIP(hipGetLastError());
   return Status{};
 }

@@ -148,10 +148,11 @@ Status create(const srt_grid *grid, double R, const double *angles, int32_t na,
   // z-neighbouring cells (A34^T), 8 x-neighbouring pixels (A12^T).
   const int64_t L = p->live;
   const int me = vdt == SRT_F64 ? kE64 : kE32;
-  if (st.ok()) st = build_tiled(p->a12, RowGrid{na, L, 8, 32, true}, me, s, &p->t12);
-  if (st.ok()) st = build_tiled(p->a12t, RowGrid{grid->ms, grid->ms, 16, 16, false}, me, s, &p->t12t);
-  if (st.ok()) st = build_tiled(p->a34, RowGrid{nh, nl, 16, 16, true}, me, s, &p->t34);
-  if (st.ok()) st = build_tiled(p->a34t, RowGrid{L, grid->mz, 16, 16, false}, me, s, &p->t34t);
+  const int64_t bh = kRB / 16;  // 16 or 8
+  if (st.ok()) st = build_tiled(p->a12, RowGrid{na, L, 8, kRB / 8, true}, me, s, &p->t12);
+  if (st.ok()) st = build_tiled(p->a12t, RowGrid{grid->ms, grid->ms, bh, 16, false}, me, s, &p->t12t);
+  if (st.ok()) st = build_tiled(p->a34, RowGrid{nh, nl, 16, bh, true}, me, s, &p->t34);
+  if (st.ok()) st = build_tiled(p->a34t, RowGrid{L, grid->mz, bh, 16, false}, me, s, &p->t34t);
   if (!st.ok()) return bail(st);
   p->magic = kPlanMagic;
   *out = p;

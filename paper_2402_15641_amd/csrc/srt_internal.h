@@ -80,13 +80,29 @@ Status build_csr_pair(Coo *pieces, int64_t nrows, int64_t ncols, srt_dtype wdtyp
 Status compact_a12(Coo *pieces, int32_t nl, int64_t npix, hipStream_t s, int32_t *live);
 
 // ---- row-blocked operator format (tiled.hip)
+// Workgroup shape of the stage kernels. Two shapes were measured at 256^3:
+// 8 wavefronts per workgroup (128 rows, 64 staged columns per chunk, two
+// workgroups per CU) ran the forward stages 5-10% faster than 16 wavefronts
+// (256 rows, 128 columns, one workgroup per CU) and the pair 2% faster: a
+// second workgroup keeps a CU busy while the first waits at a chunk barrier,
+// at the price of less reuse of each staged column.
+#ifndef SRT_WG_WAVES
+#define SRT_WG_WAVES 8
+#endif
+#if SRT_WG_WAVES == 16
 constexpr int kRB = 256;   // rows per block (one workgroup)
-constexpr int kQ = 4;      // rows per quad: a lane group runs a quad in lockstep
-constexpr int kNQ = kRB / kQ;  // quads per block
 constexpr int kC = 128;    // columns staged in LDS per chunk
 constexpr int kE32 = 1920; // padded entries staged in LDS per chunk (FP32 values)
 constexpr int kE64 = 960;  // padded entries staged in LDS per chunk (FP64 values)
-constexpr int kNW = 16;    // wavefronts per workgroup
+#else
+constexpr int kRB = 128;
+constexpr int kC = 64;
+constexpr int kE32 = 940;  // two workgroups' double buffers fit one CU's LDS
+constexpr int kE64 = 470;
+#endif
+constexpr int kQ = 4;      // rows per quad: a lane group runs a quad in lockstep
+constexpr int kNQ = kRB / kQ;  // quads per block
+constexpr int kNW = SRT_WG_WAVES;  // wavefronts per workgroup
 
 // The operator's rows viewed as an n1 x n2 grid (row = i1 * n2 + i2), cut
 // into b1 x b2 blocks (b1 * b2 == kRB; edge blocks are partly empty). Within
