@@ -4,8 +4,9 @@ Workload: grids drawn uniformly from 64^3, 128^3 and 192^3 on [-1,1]^3,
 apertures N columns x N heights x 4N radii on a cylinder of radius 1.3
 (l_max = distance to the farthest voxel corner); 70% forward requests
 (ellipsoid phantoms, 16 per grid, seeded) and 30% adjoint requests (N(0,1)
-data, 16 per grid); Poisson arrivals at each rate; plans resident on the
-device; admission by device-memory footprint (default budget 16 GiB);
+data, 16 per grid); Poisson arrivals at each rate (the two highest default
+rates exceed what one GPU serves, so there the throughput is the capacity);
+plans resident on the device; admission by device-memory footprint (default budget 16 GiB);
 continuous batching (up to 8 per batch) on 4 streams. Run once with FP32
 operator weights and once with BF16 weights (FP32 accumulation).
 
@@ -25,7 +26,7 @@ import numpy as np
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--rates", type=float, nargs="+", default=[50, 100, 200, 500, 1000, 2000])
+    ap.add_argument("--rates", type=float, nargs="+", default=[50, 100, 200, 500, 1000, 2000, 5000, 10000])
     ap.add_argument("--weights", nargs="+", default=["f32", "bf16"])
     ap.add_argument("--max-requests", type=int, default=5000)
     ap.add_argument("--seconds", type=float, default=10.0,
@@ -62,6 +63,23 @@ def main():
                 p.forward(torch.stack(pools[n][0][:b]))
                 p.adjoint(torch.stack(pools[n][1][:b]))
         torch.cuda.synchronize()
+        # device time per request in full batches of 8, and the request rate
+        # one GPU sustains on this mix when it does nothing else
+        per_req = {}
+        for key, p in plans.items():
+            n = int(key[1:])
+            for kind, pool, fn in (("fwd", pools[n][0], p.forward), ("adj", pools[n][1], p.adjoint)):
+                x = torch.stack(pool[:8])
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(5):
+                    fn(x)
+                e1.record()
+                torch.cuda.synchronize()
+                per_req[f"{key}_{kind}"] = e0.elapsed_time(e1) / 5 / 8
+        mix_ms = sum((0.7 if k.endswith("fwd") else 0.3) / len(plans) * v for k, v in per_req.items())
+        print(json.dumps({"weights": w, "device_ms_per_request_batch8": per_req,
+                          "device_bound_capacity_rps": 1000.0 / mix_ms}), flush=True)
         for rate in args.rates:
             rng = np.random.default_rng(int(rate) + (0 if w == "f32" else 1))
             nreq = int(min(args.max_requests, max(200, rate * args.seconds)))

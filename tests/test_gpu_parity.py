@@ -225,3 +225,27 @@ def test_pact256_sampled_forward_and_sparse_adjoint():
         Gp = osrt.adj_stage2(a34s, din[a], ap.n_radii, ap.mz)
         ref += osrt.adj_stage1(geo.assemble_a12(ap, ap.angles[a]), Gp, ap.ms)
     assert rel_l2(Fp, ref) <= 1e-5
+
+
+def test_pact256_batch_over_4gib_matches_single():
+    """A batch of 11 at 256^3 makes every stage's dense operand span 4 GiB or
+    more except stage 1's forward input, so those stages stage their rows by
+    global rather than buffer copies (32-bit offsets would overflow). Batch
+    items must equal the single applies bitwise."""
+    ap = config("pact256")
+    F = _t(phantoms.phantom(ap), torch.float32)
+    plan = _plan(ap, "f32")
+    Y1 = plan.forward(F)
+    Fp1 = plan.adjoint(Y1)
+    n = 11
+    L = plan.info["live_radii"]
+    assert L * ap.mz * n * ap.n_angles * 4 >= 1 << 32  # stage-2 forward operand
+    Fb = torch.stack([F * (1.0 + 0.25 * i) for i in range(n)])
+    Fb[0] = F
+    Fb[-1] = F
+    Yb = plan.forward(Fb)
+    assert torch.equal(Yb[0], Y1) and torch.equal(Yb[-1], Y1)
+    Fpb = plan.adjoint(Yb)
+    assert torch.equal(Fpb[0], Fp1) and torch.equal(Fpb[-1], Fp1)
+    # the scaled items are scaled copies up to FP32 rounding
+    assert rel_l2(_np(Yb[4]), 2.0 * _np(Y1)) <= 1e-6
