@@ -13,9 +13,12 @@ Contents (each function cites the passage of the paper it follows):
   closed_forms  exact transforms of disks and balls used as pins
   brute         brute-force samplers of the discrete operator and of the
                 plain surface integral (Sec. 2, spherical coordinates)
+  cgls          least-squares reconstruction with the matched pair (conjugate
+                gradients on the normal equations), the use the paper gives
+                for an exactly matched adjoint
 
 Precision: float64 throughout. Every function here is pinned by a
 -m "not gpu" test against something other than itself (closed forms,
 brute-force sampling, invariants, symmetries); see tests/test_oracle_*.py.
 """
-from . import geometry, srt, closed_forms, brute  # noqa: F401
+from . import geometry, srt, closed_forms, brute, cgls  # noqa: F401
