@@ -181,6 +181,38 @@ srt_status srt_plan_set_timing(srt_plan *plan, int32_t enable);
 srt_status srt_plan_stage_times(const srt_plan *plan, int32_t adjoint, int32_t n_stages,
                                 double *total_ms, int32_t *n_calls);
 
+/*
+ * srt_cgls -- least-squares reconstruction with the matched pair: n_iter
+ * iterations of conjugate gradients on the normal equations
+ * A^T A f = A^T g (the CGLS arrangement), where A is srt_forward (Alg. 1)
+ * and A^T is srt_adjoint (Alg. 2). This is the use the paper gives for an
+ * exactly matched adjoint (Sec. 1, Sec. 3.2): the iterates minimise
+ * ||A f - g||_2 over growing Krylov spaces. Each batch item is its own
+ * problem.
+ *   vol        device [batch][mz][ms][ms]: the starting point f0 on entry,
+ *              f after n_iter iterations on return
+ *   data       device [batch][n_angles][n_z][n_radii]: g (read only)
+ *   batch      1 .. 65535
+ *   n_iter     >= 0
+ *   resid      host array of (n_iter + 1) * batch doubles, or NULL:
+ *              resid[k * batch + b] = ||A^T (g - A f_k)||_2 of item b
+ *              (the call then returns after the stream has finished)
+ *   workspace  device scratch of at least srt_cgls_workspace() bytes (not
+ *              shared with concurrent calls)
+ * Inner products are reduced in FP64 in a fixed order; step lengths stay on
+ * the device (no host round trip per iteration). Asynchronous on hip_stream
+ * unless resid is given.
+ * Errors: EINVAL (NULL pointers, batch or n_iter out of range, workspace too
+ * small), EDEVICE.
+ */
+srt_status srt_cgls(srt_plan *plan, void *vol, const void *data, int32_t batch,
+                    int32_t n_iter, double *resid, void *workspace,
+                    size_t workspace_bytes, void *hip_stream);
+
+/* Workspace bytes srt_cgls needs for `batch` items and `n_iter` iterations. */
+srt_status srt_cgls_workspace(const srt_plan *plan, int32_t batch, int32_t n_iter,
+                              size_t *bytes);
+
 /* Thread-local description of the last error on the calling thread. */
 const char *srt_last_error(void);
 

@@ -23,7 +23,8 @@ MODES = {"auto": 0, "stored": 1, "onthefly": 2}
 # Every entry point declared in include/srt.h.
 SYMBOLS = ("srt_plan_create", "srt_forward", "srt_adjoint", "srt_plan_destroy",
            "srt_plan_footprint", "srt_plan_get_info", "srt_plan_export_coo",
-           "srt_plan_set_timing", "srt_plan_stage_times", "srt_last_error")
+           "srt_plan_set_timing", "srt_plan_stage_times", "srt_cgls", "srt_cgls_workspace",
+           "srt_last_error")
 STAGES = 5
 
 
@@ -70,6 +71,8 @@ def lib() -> ctypes.CDLL:
     L.srt_plan_set_timing.argtypes = [P, I32]
     L.srt_plan_stage_times.argtypes = [P, I32, I32, ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(I32)]
+    L.srt_cgls.argtypes = [P, P, P, I32, I32, P, P, SZ, P]
+    L.srt_cgls_workspace.argtypes = [P, I32, I32, ctypes.POINTER(SZ)]
     for name in SYMBOLS[:-1]:
         getattr(L, name).restype = ctypes.c_int
     L.srt_last_error.argtypes = []
@@ -176,3 +179,24 @@ def srt_plan_stage_times(plan: int, adjoint: bool):
     _check(lib().srt_plan_stage_times(plan, 1 if adjoint else 0, STAGES, tot, ctypes.byref(n)),
            "srt_plan_stage_times")
     return list(tot), n.value
+
+
+def srt_cgls_workspace(plan: int, batch: int, n_iter: int) -> int:
+    """Workspace bytes srt_cgls needs."""
+    b = ctypes.c_size_t()
+    _check(lib().srt_cgls_workspace(plan, int(batch), int(n_iter), ctypes.byref(b)),
+           "srt_cgls_workspace")
+    return b.value
+
+
+def srt_cgls(plan: int, vol, data, batch: int, n_iter: int, workspace, want_resid=True,
+             stream=None):
+    """n_iter CGLS iterations in place on vol (device tensors); returns the
+    residual norms ||A^T (g - A f_k)|| as an (n_iter + 1, batch) array, or
+    None when want_resid is False (then the call is asynchronous)."""
+    resid = np.zeros((int(n_iter) + 1, int(batch)), np.float64) if want_resid else None
+    _check(lib().srt_cgls(plan, vol.data_ptr(), data.data_ptr(), int(batch), int(n_iter),
+                          None if resid is None else resid.ctypes.data, workspace.data_ptr(),
+                          workspace.numel() * workspace.element_size(), _stream_ptr(stream)),
+           "srt_cgls")
+    return resid

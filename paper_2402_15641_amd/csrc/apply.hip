@@ -137,8 +137,8 @@ template <> struct Quad4<double, double> {
 };
 
 // One chunk's worth of LDS: staged dense rows (row kC stays zero and is what
-// padding entries point at), the entries' local columns and weights (as
-// stored), and the quads' entry offsets.
+// padding entries point at) and the entries' local columns and weights (as
+// stored). The quads' entry offsets and first entries travel in registers.
 template <typename T, typename WT> struct ChunkLds {
   using V16 = typename Vec16<T>::type;
   static constexpr int E = TileShape<T>::E;
@@ -146,7 +146,6 @@ template <typename T, typename WT> struct ChunkLds {
   V16 *dense;
   int32_t *col;
   uint32_t *w;
-  int32_t *seg;
 };
 
 // One workgroup (one per CU) = one row block x one slice of the dense index.
@@ -165,6 +164,10 @@ template <typename T, typename WT> struct ChunkLds {
 // padded so the rows advance together), kQ * NV dense vectors and does
 // kQ * NV * VS fused multiply-adds per lane. The next step's entries are read
 // before this step's products, so their LDS latency overlaps the dense reads.
+// A group's offsets into chunk c+1 and its first step's entries are loaded
+// from memory into registers while chunk c is consumed (the offsets one chunk
+// earlier still), so a chunk starts with its dense reads, not with two
+// dependent LDS round trips.
 // MODE 1: the dense width D is a multiple of VS and the dense operand spans
 // less than 4 GiB, so rows are staged in 16-byte pieces through buffer
 // copies. MODE 2: 16-byte pieces through global copies (operand of 4 GiB or
@@ -189,8 +192,7 @@ __device__ __forceinline__ void tiled_body(const int32_t *__restrict__ blk_rows,
   __shared__ V16 dense0[(kC + 1) * PIECES], dense1[(kC + 1) * PIECES];
   __shared__ int32_t col0[E], col1[E];
   __shared__ uint32_t w0[L::WWORDS], w1[L::WWORDS];
-  __shared__ int32_t seg0[kNQ + 1], seg1[kNQ + 1];
-  const L buf0{dense0, col0, w0, seg0}, buf1{dense1, col1, w1, seg1};
+  const L buf0{dense0, col0, w0}, buf1{dense1, col1, w1};
 
   const int bid = remap ? xcd_local(blockIdx.x, gridDim.x) : (int)blockIdx.x;
   const int blk = bid % nblk, slice = bid / nblk;
@@ -270,11 +272,6 @@ __device__ __forceinline__ void tiled_body(const int32_t *__restrict__ blk_rows,
         const int i = j * 64 + lane;
         if (i < nw) buf_dma4(rw, (uint32_t)i * 4u, b.w + j * 64);
       }
-      const auto rq = buf_rsrc(qseg + (size_t)c * (kNQ + 1), (kNQ + 1) * 4u);
-      for (int j = wave; j * 64 < kNQ + 1; j += kNW) {
-        const int i = j * 64 + lane;
-        if (i < kNQ + 1) buf_dma4(rq, (uint32_t)i * 4u, b.seg + j * 64);
-      }
     } else {
       for (int j = wave; j * 64 < ne; j += kNW) {
         const int i = j * 64 + lane;
@@ -285,20 +282,34 @@ __device__ __forceinline__ void tiled_body(const int32_t *__restrict__ blk_rows,
         const int i = j * 64 + lane;
         if (i < nw) lds_dma4(wsrc + i, b.w + j * 64);
       }
-      for (int j = wave; j * 64 < kNQ + 1; j += kNW) {
-        const int i = j * 64 + lane;
-        if (i < kNQ + 1) lds_dma4(qseg + (size_t)c * (kNQ + 1) + i, b.seg + j * 64);
-      }
     }
   };
-  // This lane group's quad over one staged chunk.
-  auto consume = [&](const L &b) {
-    const int q = wave * GROUPS + grp;
-    const int e0 = b.seg[q], e1 = b.seg[q + 1];
-    const int ef = min(e0, E - kQ);  // a quad may start at the chunk's very end
-    int4 cn = *reinterpret_cast<const int4 *>(b.col + ef);
+  // This lane group's quad: its entry range in chunk c and its first step's
+  // entries (columns and weights), read from memory, not from LDS.
+  const int q = wave * GROUPS + grp;
+  struct Head {
+    int e0, e1;
+    int4 cn;
     T wn[kQ];
-    Quad4<T, WT>::load(b.w, ef, wn);
+  };
+  auto load_range = [&](int c, Head &h) {
+    const int32_t *qs = qseg + (size_t)c * (kNQ + 1) + q;
+    h.e0 = qs[0];
+    h.e1 = qs[1];
+  };
+  auto load_first = [&](int c, Head &h) {
+    // an empty segment reads the chunk's first entries instead (in range)
+    const int e = chunk_ent[c] + (h.e0 < h.e1 ? h.e0 : 0);
+    h.cn = *reinterpret_cast<const int4 *>(ent_col + e);
+    Quad4<T, WT>::load(reinterpret_cast<const uint32_t *>(ent_w), e, h.wn);
+  };
+  // This lane group's quad over one staged chunk.
+  auto consume = [&](const L &b, const Head &h) {
+    const int e0 = h.e0, e1 = h.e1;
+    int4 cn = h.cn;
+    T wn[kQ];
+#pragma unroll
+    for (int j = 0; j < kQ; ++j) wn[j] = h.wn[j];
     // Keep the loop's own entry reads where they are written (a step ahead):
     // without this the compiler merges them with these first reads into one
     // read at the top of the loop, which stalls every step on it.
@@ -332,9 +343,13 @@ __device__ __forceinline__ void tiled_body(const int32_t *__restrict__ blk_rows,
 
   if (c0 < c1) {
     int32_t cols_a[PPW], cols_b[PPW];
+    Head hc, hn, hnn;  // chunk c, c+1 (range and first entries), c+2 (range)
     if constexpr (VEC) load_cols(c0, cols_a);
     stage(c0, buf0, cols_a);
     if (VEC && c0 + 1 < c1) load_cols(c0 + 1, cols_b);
+    load_range(c0, hc);
+    if (c0 + 1 < c1) load_range(c0 + 1, hn);
+    load_first(c0, hc);
     wait_vmem();
     __syncthreads();
     // one chunk: copy the next into `nxt`, consume `cur`, wait, publish
@@ -343,10 +358,14 @@ __device__ __forceinline__ void tiled_body(const int32_t *__restrict__ blk_rows,
       if (c + 1 < c1) {
         stage(c + 1, nxt, cols_next);
         if (VEC && c + 2 < c1) load_cols(c + 2, cols_after);
+        load_first(c + 1, hn);
+        if (c + 2 < c1) load_range(c + 2, hnn);
       }
-      consume(cur);
+      consume(cur, hc);
       wait_vmem();
       __syncthreads();
+      hc = hn;
+      hn = hnn;
     };
     for (int c = c0; c < c1; c += 2) {
       step(c, buf0, buf1, cols_b, cols_a);
@@ -597,18 +616,6 @@ Status get_workspace(srt_plan *p, int32_t B, void *ws, size_t ws_bytes, hipStrea
   return Status{};
 }
 
-struct DeviceScope {
-  int prev = -1;
-  hipError_t err = hipSuccess;
-  explicit DeviceScope(int dev) {
-    err = hipGetDevice(&prev);
-    if (err == hipSuccess && prev != dev) err = hipSetDevice(dev);
-  }
-  ~DeviceScope() {
-    if (prev >= 0) (void)hipSetDevice(prev);
-  }
-};
-
 Status apply(srt_plan *p, const void *in, void *out, int32_t B, void *ws, size_t ws_bytes,
              hipStream_t s, bool adjoint) {
   if (!p || p->magic != kPlanMagic) return fail(SRT_EINVAL, "plan is NULL or not a live plan");
@@ -657,6 +664,11 @@ Status apply(srt_plan *p, const void *in, void *out, int32_t B, void *ws, size_t
 }
 
 }  // namespace
+
+Status apply_plan(srt_plan *p, const void *in, void *out, int32_t batch, void *ws,
+                  size_t ws_bytes, hipStream_t s, bool adjoint) {
+  return apply(p, in, out, batch, ws, ws_bytes, s, adjoint);
+}
 
 size_t workspace_bytes(const srt_plan *p, int32_t batch) {
   return 2 * align_up(buffer_elems(p, batch) * dtype_size(p->vdtype));

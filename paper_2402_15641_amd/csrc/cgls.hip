@@ -1,0 +1,247 @@
+// Least-squares reconstruction with the matched SRT pair: conjugate gradients
+// on the normal equations A^T A f = A^T g (the CGLS arrangement), applying
+// only the forward (Alg. 1) and the adjoint (Alg. 2) of a plan. An exactly
+// matched adjoint is what makes these iterations consistent (Sec. 3.2).
+//
+// Per batch item b, an independent problem:
+//   r = g - A f,  s = A^T r,  p = s,  gamma = ||s||^2
+//   repeat:  q = A p,  alpha = gamma / ||q||^2
+//            f += alpha p,  r -= alpha q
+//            s = A^T r,  gamma' = ||s||^2,  p = s + (gamma'/gamma) p
+// All vector work and the scalars stay on the device: inner products are
+// reduced in FP64 in a fixed order (so runs are bitwise repeatable), and the
+// step lengths are read by the update kernels from device memory, so an
+// iteration never waits for the host.
+#include <cstdint>
+#include <utility>
+
+#include "srt_internal.h"
+
+namespace srt {
+namespace {
+
+constexpr int kRedThreads = 256;
+constexpr int kRedBlocks = 1024;  // partial sums per batch item
+
+size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// 16-byte vectors of T (4 floats or 2 doubles), used when every batch item's
+// vector starts 16-byte aligned (its length is a multiple of the width).
+template <typename T> struct V;
+template <> struct V<float> { using t = float4; static constexpr int n = 4; };
+template <> struct V<double> { using t = double2; static constexpr int n = 2; };
+
+// part[b * kRedBlocks + blk] = sum over this block's share of item b of x*y,
+// in FP64: each thread sums a fixed stride of the item, then a fixed tree.
+template <typename T, bool VEC>
+__global__ __launch_bounds__(kRedThreads) void k_dot_partial(const T *__restrict__ x,
+                                                             const T *__restrict__ y, int64_t n,
+                                                             double *__restrict__ part) {
+  __shared__ double red[kRedThreads];
+  const int b = blockIdx.y, blk = blockIdx.x, t = threadIdx.x;
+  const T *xb = x + (size_t)b * n, *yb = y + (size_t)b * n;
+  const int64_t stride = (int64_t)kRedBlocks * kRedThreads;
+  double acc = 0.0;
+  if constexpr (VEC) {
+    using VT = typename V<T>::t;
+    constexpr int W = V<T>::n;
+    const VT *xv = reinterpret_cast<const VT *>(xb), *yv = reinterpret_cast<const VT *>(yb);
+    for (int64_t i = (int64_t)blk * kRedThreads + t; i < n / W; i += stride) {
+      const VT a = xv[i], c = yv[i];
+      const T *as = reinterpret_cast<const T *>(&a), *cs = reinterpret_cast<const T *>(&c);
+#pragma unroll
+      for (int k = 0; k < W; ++k) acc += (double)as[k] * (double)cs[k];
+    }
+  } else {
+    for (int64_t i = (int64_t)blk * kRedThreads + t; i < n; i += stride)
+      acc += (double)xb[i] * (double)yb[i];
+  }
+  red[t] = acc;
+  __syncthreads();
+  for (int w = kRedThreads / 2; w > 0; w >>= 1) {
+    if (t < w) red[t] += red[t + w];
+    __syncthreads();
+  }
+  if (t == 0) part[(size_t)b * kRedBlocks + blk] = red[0];
+}
+
+// out[b] = sum of item b's partials in block order; optionally hist[b] = sqrt.
+__global__ void k_dot_final(const double *__restrict__ part, int batch, double *__restrict__ out,
+                            double *__restrict__ hist) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= batch) return;
+  double s = 0.0;
+  for (int i = 0; i < kRedBlocks; ++i) s += part[(size_t)b * kRedBlocks + i];
+  out[b] = s;
+  if (hist) hist[b] = sqrt(s);
+}
+
+__device__ __forceinline__ double ratio(double num, double den) { return den > 0.0 ? num / den : 0.0; }
+
+// y = a * x + y  (XPAY false)  or  y = x + a * y  (XPAY true), per batch item
+// b with a = sign * num[b] / den[b] (a zero denominator gives a = 0).
+template <typename T, bool VEC, bool XPAY>
+__global__ void k_update(T *__restrict__ y, const T *__restrict__ x, const double *__restrict__ num,
+                         const double *__restrict__ den, double sign, int64_t n) {
+  const int b = blockIdx.y;
+  const T a = (T)(sign * ratio(num[b], den[b]));
+  T *yb = y + (size_t)b * n;
+  const T *xb = x + (size_t)b * n;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  auto op = [&](T xv, T yv) { return XPAY ? fma(a, yv, xv) : fma(a, xv, yv); };
+  if constexpr (VEC) {
+    using VT = typename V<T>::t;
+    constexpr int W = V<T>::n;
+    VT *yv = reinterpret_cast<VT *>(yb);
+    const VT *xv = reinterpret_cast<const VT *>(xb);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n / W; i += stride) {
+      VT u = yv[i];
+      const VT w = xv[i];
+      T *us = reinterpret_cast<T *>(&u);
+      const T *ws = reinterpret_cast<const T *>(&w);
+#pragma unroll
+      for (int k = 0; k < W; ++k) us[k] = op(ws[k], us[k]);
+      yv[i] = u;
+    }
+  } else {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+      yb[i] = op(xb[i], yb[i]);
+  }
+}
+
+// r = g - r   (r holds A f on entry)
+template <typename T>
+__global__ void k_rsub(T *__restrict__ r, const T *__restrict__ g, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    r[i] = g[i] - r[i];
+}
+
+struct Layout {
+  size_t r, q, s, p, ws, scal, part, hist, total;  // byte offsets
+  size_t ws_bytes;
+};
+
+Layout layout(const srt_plan *p, int32_t batch, int32_t n_iter) {
+  const Geometry &g = p->geo;
+  const size_t es = dtype_size(p->vdtype);
+  const size_t vol = (size_t)batch * g.mz * g.ms * g.ms * es;
+  const size_t dat = (size_t)batch * g.na * g.nh * g.nl * es;
+  Layout L{};
+  size_t o = 0;
+  L.r = o; o += align_up(dat);
+  L.q = o; o += align_up(dat);
+  L.s = o; o += align_up(vol);
+  L.p = o; o += align_up(vol);
+  L.ws_bytes = workspace_bytes(p, batch);
+  L.ws = o; o += align_up(L.ws_bytes);
+  L.scal = o; o += align_up(sizeof(double) * 3 * batch);  // gamma, gamma', delta
+  L.part = o; o += align_up(sizeof(double) * kRedBlocks * batch);
+  L.hist = o; o += align_up(sizeof(double) * (size_t)(n_iter + 1) * batch);
+  L.total = o;
+  return L;
+}
+
+unsigned grid_for(int64_t n) {
+  const int64_t b = (n + 255) / 256;
+  return (unsigned)(b < 8192 ? (b > 0 ? b : 1) : 8192);
+}
+
+template <typename T>
+Status run(srt_plan *plan, T *f, const T *g, int32_t B, int32_t n_iter, double *resid, char *w,
+           const Layout &L, hipStream_t st) {
+  const Geometry &geo = plan->geo;
+  const int64_t nv = (int64_t)geo.mz * geo.ms * geo.ms, nd = (int64_t)geo.na * geo.nh * geo.nl;
+  T *r = (T *)(w + L.r), *q = (T *)(w + L.q), *s = (T *)(w + L.s), *p = (T *)(w + L.p);
+  void *ws = w + L.ws;
+  double *gam = (double *)(w + L.scal), *gam2 = gam + B, *del = gam + 2 * B;
+  double *part = (double *)(w + L.part), *hist = (double *)(w + L.hist);
+  constexpr int W = V<T>::n;
+  // vector kernels when every item's vector is a whole number of 16-byte
+  // vectors and the caller's arrays are 16-byte aligned (workspace arrays are)
+  const bool fv = nv % W == 0 && (uintptr_t)f % 16 == 0;
+  auto dot = [&](const T *x, const T *y, int64_t n, bool vec, double *out, double *h) -> Status {
+    if (vec)
+      hipLaunchKernelGGL((k_dot_partial<T, true>), dim3(kRedBlocks, B), dim3(kRedThreads), 0, st, x, y, n, part);
+    else
+      hipLaunchKernelGGL((k_dot_partial<T, false>), dim3(kRedBlocks, B), dim3(kRedThreads), 0, st, x, y, n, part);
+    hipLaunchKernelGGL(k_dot_final, dim3((B + 63) / 64), dim3(64), 0, st, part, B, out, h);
+    SRT_HIP(hipGetLastError());
+    return Status{};
+  };
+  auto update = [&](T *y, const T *x, int64_t n, bool vec, bool xpay, const double *num,
+                    const double *den, double sign) -> Status {
+    const dim3 grid(grid_for(vec ? n / W : n), B);
+    auto go = [&](auto kern) {
+      hipLaunchKernelGGL(kern, grid, dim3(256), 0, st, y, x, num, den, sign, n);
+    };
+    if (xpay) {
+      if (vec) go(k_update<T, true, true>); else go(k_update<T, false, true>);
+    } else {
+      if (vec) go(k_update<T, true, false>); else go(k_update<T, false, false>);
+    }
+    SRT_HIP(hipGetLastError());
+    return Status{};
+  };
+  auto fwd = [&](const T *in, T *out) { return apply_plan(plan, in, out, B, ws, L.ws_bytes, st, false); };
+  auto adj = [&](const T *in, T *out) { return apply_plan(plan, in, out, B, ws, L.ws_bytes, st, true); };
+  const bool vv = nv % W == 0, dv = nd % W == 0;  // workspace vectors
+
+  SRT_TRY(fwd(f, r));
+  hipLaunchKernelGGL(k_rsub<T>, dim3(grid_for(nd * B)), dim3(256), 0, st, r, g, nd * B);
+  SRT_HIP(hipGetLastError());
+  SRT_TRY(adj(r, s));
+  SRT_HIP(hipMemcpyAsync(p, s, sizeof(T) * nv * B, hipMemcpyDeviceToDevice, st));
+  SRT_TRY(dot(s, s, nv, vv, gam, hist));
+  for (int k = 1; k <= n_iter; ++k) {
+    SRT_TRY(fwd(p, q));
+    SRT_TRY(dot(q, q, nd, dv, del, nullptr));
+    SRT_TRY(update(f, p, nv, fv, false, gam, del, 1.0));   // f += alpha p
+    SRT_TRY(update(r, q, nd, dv, false, gam, del, -1.0));  // r -= alpha q
+    SRT_TRY(adj(r, s));
+    SRT_TRY(dot(s, s, nv, vv, gam2, hist + (size_t)k * B));
+    SRT_TRY(update(p, s, nv, vv, true, gam2, gam, 1.0));   // p = s + beta p
+    std::swap(gam, gam2);
+  }
+  if (resid) {
+    SRT_HIP(hipMemcpyAsync(resid, hist, sizeof(double) * (size_t)(n_iter + 1) * B,
+                           hipMemcpyDeviceToHost, st));
+    SRT_HIP(hipStreamSynchronize(st));
+  }
+  return Status{};
+}
+
+}  // namespace
+}  // namespace srt
+
+extern "C" {
+
+srt_status srt_cgls_workspace(const srt_plan *plan, int32_t batch, int32_t n_iter, size_t *bytes) {
+  using namespace srt;
+  if (!plan || plan->magic != kPlanMagic) return fail(SRT_EINVAL, "plan is NULL or not a live plan").code;
+  if (!bytes || batch <= 0 || n_iter < 0)
+    return fail(SRT_EINVAL, "bytes must be non-NULL, batch >= 1 and n_iter >= 0").code;
+  *bytes = layout(plan, batch, n_iter).total;
+  return SRT_OK;
+}
+
+srt_status srt_cgls(srt_plan *plan, void *vol, const void *data, int32_t batch, int32_t n_iter,
+                    double *resid, void *workspace, size_t workspace_bytes, void *hip_stream) {
+  using namespace srt;
+  if (!plan || plan->magic != kPlanMagic) return fail(SRT_EINVAL, "plan is NULL or not a live plan").code;
+  if (!vol || !data) return fail(SRT_EINVAL, "NULL volume or data").code;
+  if (batch <= 0 || batch > 65535 || n_iter < 0)
+    return fail(SRT_EINVAL, "batch must be in [1, 65535] and n_iter >= 0").code;
+  const Layout L = layout(plan, batch, n_iter);
+  if (!workspace || workspace_bytes < L.total)
+    return fail(SRT_EINVAL, "workspace is NULL or smaller than srt_cgls_workspace reports").code;
+  DeviceScope ds(plan->device);
+  if (ds.err != hipSuccess) return hip_fail(ds.err, "hipSetDevice").code;
+  hipStream_t st = (hipStream_t)hip_stream;
+  char *w = (char *)workspace;
+  if (plan->vdtype == SRT_F64)
+    return run<double>(plan, (double *)vol, (const double *)data, batch, n_iter, resid, w, L, st).code;
+  return run<float>(plan, (float *)vol, (const float *)data, batch, n_iter, resid, w, L, st).code;
+}
+
+}  // extern "C"

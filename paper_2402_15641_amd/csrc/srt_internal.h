@@ -164,6 +164,23 @@ struct srt_plan {
 namespace srt {
 constexpr uint32_t kPlanMagic = 0x53525431u;  // "SRT1"
 size_t workspace_bytes(const srt_plan *p, int32_t batch);
+// One forward (Alg. 1) or adjoint (Alg. 2) apply of `batch` items on stream s
+// (what srt_forward / srt_adjoint run; arguments validated there as well).
+Status apply_plan(srt_plan *p, const void *in, void *out, int32_t batch, void *ws,
+                  size_t ws_bytes, hipStream_t s, bool adjoint);
+
+// Makes `dev` the current device for the scope's lifetime.
+struct DeviceScope {
+  int prev = -1;
+  hipError_t err = hipSuccess;
+  explicit DeviceScope(int dev) {
+    err = hipGetDevice(&prev);
+    if (err == hipSuccess && prev != dev) err = hipSetDevice(dev);
+  }
+  ~DeviceScope() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
 size_t dtype_size(srt_dtype t);
 void clear_timing(srt_plan *p);
 }  // namespace srt

@@ -100,6 +100,24 @@ class SRTPlan:
         _, ws = self.footprint(batch)
         return torch.empty(ws, dtype=torch.uint8, device=self.device)
 
+    def cgls(self, data: torch.Tensor, n_iter: int, vol0: torch.Tensor | None = None,
+             workspace=None, want_resid: bool = True, stream=None):
+        """Least-squares reconstruction: n_iter CGLS iterations for
+        min ||A f - data||, starting from vol0 (zeros if None). Returns
+        (f, residual norms ||A^T (data - A f_k)|| per iteration and batch item)."""
+        batch = self._check(data, self.data_shape, "data")
+        shape = self.vol_shape if data.dim() == 3 else (batch,) + self.vol_shape
+        if vol0 is None:
+            f = torch.zeros(shape, dtype=self.dtype, device=self.device)
+        else:
+            self._check(vol0, self.vol_shape, "vol0")
+            f = vol0.clone()
+        if workspace is None:
+            workspace = torch.empty(B.srt_cgls_workspace(self.handle, batch, n_iter),
+                                    dtype=torch.uint8, device=self.device)
+        resid = B.srt_cgls(self.handle, f, data, batch, n_iter, workspace, want_resid, stream)
+        return f, resid
+
     def export_coo(self, which: int):
         return B.srt_plan_export_coo(self.handle, which)
 

@@ -77,3 +77,6 @@ def test_null_plan_calls():
     assert L.srt_plan_footprint(None, 1, ctypes.byref(r), None) == B.SRT_EINVAL
     n = ctypes.c_int64()
     assert L.srt_plan_export_coo(None, 0, 0, ctypes.byref(n), None, None, None) == B.SRT_EINVAL
+    assert L.srt_cgls(None, None, None, 1, 1, None, None, 0, None) == B.SRT_EINVAL
+    assert "plan" in B.srt_last_error()
+    assert L.srt_cgls_workspace(None, 1, 1, ctypes.byref(r)) == B.SRT_EINVAL
