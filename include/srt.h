@@ -108,6 +108,23 @@ srt_status srt_plan_create(const srt_grid *grid, double cyl_radius,
                            srt_plan **out);
 
 /*
+ * srt_plan_create_columns -- as srt_plan_create, with the sensor columns at
+ * arbitrary (x, y) positions instead of on a cylinder. Sec. 2 needs only
+ * that each group of sensors lies on one line parallel to z (sharing the
+ * first circular transform); A34 is shared by all columns as before.
+ *   col_xy   host, n_cols (x, y) pairs (column a at col_xy[2a], col_xy[2a+1]),
+ *            finite; a column may stand anywhere, inside the grid included
+ *   n_cols   number of columns (the "n_angles" of data layouts and info)
+ * Other arguments, outputs and errors as srt_plan_create.
+ */
+srt_status srt_plan_create_columns(const srt_grid *grid, const double *col_xy,
+                                   int32_t n_cols, const double *z_pos, int32_t n_z,
+                                   const double *radii, int32_t n_radii,
+                                   srt_dtype value_dtype, srt_dtype weight_dtype,
+                                   srt_opmode mode, int32_t device, void *hip_stream,
+                                   srt_plan **out);
+
+/*
  * srt_forward -- Alg. 1 for every column and every batch item:
  * data[b][a][h][l] = sum over (l', k) of A34[(h,l),(l',k)] *
  *                    sum over p of A12_a[l', p] * vol[b][k][p].

@@ -89,9 +89,15 @@ def a12_row(ap, center, radius: float):
 
 
 def assemble_a12(ap, angle: float, rows=None) -> sp.csr_matrix:
-    """A12 for the sensor column at angle `angle` (Alg. 1 input, N_l x M_s^2).
-    `rows` restricts assembly to a subset of radius indices (others empty)."""
-    c = (ap.radius * np.cos(angle), ap.radius * np.sin(angle))
+    """A12 for the sensor column at angle `angle` on the cylinder (Alg. 1
+    input, N_l x M_s^2). `rows` restricts assembly to a subset of radius
+    indices (others empty)."""
+    return assemble_a12_at(ap, (ap.radius * np.cos(angle), ap.radius * np.sin(angle)), rows)
+
+
+def assemble_a12_at(ap, c, rows=None) -> sp.csr_matrix:
+    """A12 for the sensor column through (x, y) = c: Sec. 2 only needs the
+    sensors of a group on one line parallel to z, wherever that line is."""
     rows = range(ap.n_radii) if rows is None else rows
     ri, ci, vi = [], [], []
     for l in rows:
@@ -132,4 +138,6 @@ def assemble_a34(ap, heights=None) -> sp.csr_matrix:
 
 def assemble_all(ap):
     """All per-column A12 matrices and the shared A34."""
+    if getattr(ap, "centers", None) is not None:
+        return [assemble_a12_at(ap, c) for c in ap.column_centers], assemble_a34(ap)
     return [assemble_a12(ap, a) for a in ap.angles], assemble_a34(ap)

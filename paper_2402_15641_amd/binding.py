@@ -21,7 +21,7 @@ DTYPES = {"f32": 0, "f64": 1, "bf16": 2, "f16": 3}
 MODES = {"auto": 0, "stored": 1, "onthefly": 2}
 
 # Every entry point declared in include/srt.h.
-SYMBOLS = ("srt_plan_create", "srt_forward", "srt_adjoint", "srt_plan_destroy",
+SYMBOLS = ("srt_plan_create", "srt_plan_create_columns", "srt_forward", "srt_adjoint", "srt_plan_destroy",
            "srt_plan_footprint", "srt_plan_get_info", "srt_plan_export_coo",
            "srt_plan_set_timing", "srt_plan_stage_times", "srt_cgls", "srt_cgls_workspace",
            "srt_last_error")
@@ -62,6 +62,9 @@ def lib() -> ctypes.CDLL:
                           ctypes.c_size_t)
     L.srt_plan_create.argtypes = [ctypes.POINTER(SrtGrid), D, P, I32, P, I32, P, I32, ctypes.c_int,
                                   ctypes.c_int, ctypes.c_int, I32, P, ctypes.POINTER(P)]
+    L.srt_plan_create_columns.argtypes = [ctypes.POINTER(SrtGrid), P, I32, P, I32, P, I32,
+                                          ctypes.c_int, ctypes.c_int, ctypes.c_int, I32, P,
+                                          ctypes.POINTER(P)]
     L.srt_forward.argtypes = [P, P, P, I32, P, SZ, P]
     L.srt_adjoint.argtypes = [P, P, P, I32, P, SZ, P]
     L.srt_plan_destroy.argtypes = [P]
@@ -115,6 +118,25 @@ def srt_plan_create(ms, mz, x0, z0, dxy, dz, cyl_radius, angles, z_pos, radii,
                            _stream_ptr(stream) if stream is not False else None,
                            ctypes.byref(out))
     _check(st, "srt_plan_create")
+    return out.value
+
+
+def srt_plan_create_columns(ms, mz, x0, z0, dxy, dz, col_xy, z_pos, radii,
+                            value_dtype="f32", weight_dtype="f32", mode="auto", device=0,
+                            stream=None) -> int:
+    """Builds a plan for sensor columns at arbitrary (x, y) positions
+    (col_xy: n x 2); returns its opaque handle."""
+    L = lib()
+    grid = SrtGrid(int(ms), int(mz), float(x0), float(z0), float(dxy), float(dz))
+    xy, zp, rad = _f64(col_xy).reshape(-1, 2), _f64(z_pos), _f64(radii)
+    xy = np.ascontiguousarray(xy)
+    out = ctypes.c_void_p()
+    st = L.srt_plan_create_columns(ctypes.byref(grid), xy.ctypes.data, xy.shape[0],
+                                   zp.ctypes.data, zp.size, rad.ctypes.data, rad.size,
+                                   DTYPES[value_dtype], DTYPES[weight_dtype], MODES[mode],
+                                   int(device), _stream_ptr(stream) if stream is not False else None,
+                                   ctypes.byref(out))
+    _check(st, "srt_plan_create_columns")
     return out.value
 
 

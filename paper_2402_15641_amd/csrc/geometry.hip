@@ -2,7 +2,7 @@
 //
 // A12 (Sec. 2, circle transform in a z-slice, measure rho dphi): row a*nl + l
 // holds, for every pixel p = j*ms + i, the length of the circle of radius
-// radii[l] about column centre (R cos angles[a], R sin angles[a]) inside p.
+// radii[l] about the centre (cx[a], cy[a]) of column a inside p.
 // A34 (Sec. 2, half-circle transform, measure l dtheta, theta in [0, pi]):
 // row h*nl + l holds, for every cell (rho cell l', z slice k) with column
 // index l'*mz + k, the length of the half circle of radius radii[l] about
@@ -184,9 +184,7 @@ __global__ void a12_kernel(Geometry g, const int64_t *__restrict__ offs,
   const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (row >= (int64_t)g.na * g.nl) return;
   const int a = (int)(row / g.nl), l = (int)(row % g.nl);
-  double sa, ca;
-  sincos(g.angles[a], &sa, &ca);
-  const double cx = g.R * ca, cy = g.R * sa, r = g.radii[l];
+  const double cx = g.cx[a], cy = g.cy[a], r = g.radii[l];
   const UniformEdges xe{g.x0, g.dxy, g.ms};
   const bool fill = counts == nullptr;
   PieceEmit e{(uint64_t)row * (uint64_t)g.ms * (uint64_t)g.ms, g.ms, g.ms,

@@ -25,7 +25,7 @@ struct DeviceGuard {
   }
 };
 
-bool finite_all(const double *v, int32_t n) {
+bool finite_all(const double *v, int64_t n) {
   for (int32_t i = 0; i < n; ++i)
     if (!std::isfinite(v[i])) return false;
   return true;
@@ -55,20 +55,20 @@ void destroy_contents(srt_plan *p) {
   p->own_ws = nullptr;
 }
 
-Status create(const srt_grid *grid, double R, const double *angles, int32_t na,
+// col_xy: host [na][2] column centres (x, y).
+Status create(const srt_grid *grid, const double *col_xy, int32_t na,
               const double *zpos, int32_t nh, const double *radii, int32_t nl,
               srt_dtype vdt, srt_dtype wdt, srt_opmode mode, int32_t device, hipStream_t s,
               srt_plan **out) {
   if (!out) return fail(SRT_EINVAL, "out is NULL");
   *out = nullptr;
-  if (!grid || !angles || !zpos || !radii) return fail(SRT_EINVAL, "NULL argument");
+  if (!grid || !col_xy || !zpos || !radii) return fail(SRT_EINVAL, "NULL argument");
   if (grid->ms <= 0 || grid->mz <= 0) return fail(SRT_EINVAL, "grid sizes must be positive");
   if (!(std::isfinite(grid->x0) && std::isfinite(grid->z0) && std::isfinite(grid->dxy) &&
         std::isfinite(grid->dz)) || grid->dxy <= 0 || grid->dz <= 0)
     return fail(SRT_EINVAL, "grid origin and pitch must be finite, pitch > 0");
-  if (!std::isfinite(R) || R < 0) return fail(SRT_EINVAL, "cylinder radius must be finite and >= 0");
   if (na <= 0 || nh <= 0 || nl <= 0) return fail(SRT_EINVAL, "sample counts must be positive");
-  if (!finite_all(angles, na) || !finite_all(zpos, nh) || !finite_all(radii, nl))
+  if (!finite_all(col_xy, 2 * (int64_t)na) || !finite_all(zpos, nh) || !finite_all(radii, nl))
     return fail(SRT_EINVAL, "sample positions must be finite");
   if (radii[0] <= 0) return fail(SRT_EINVAL, "radii must be > 0");
   for (int32_t i = 1; i < nl; ++i)
@@ -99,12 +99,15 @@ Status create(const srt_grid *grid, double R, const double *angles, int32_t na,
     delete p;
     return st;
   };
-  if (hipMalloc(&p->d_geom, sizeof(double) * ((size_t)na + nh + nl)) != hipSuccess)
+  if (hipMalloc(&p->d_geom, sizeof(double) * (2 * (size_t)na + nh + nl)) != hipSuccess)
     return bail(fail(SRT_ENOMEM, "device allocation for geometry failed"));
-  std::vector<double> h((size_t)na + nh + nl);
-  std::memcpy(h.data(), angles, sizeof(double) * na);
-  std::memcpy(h.data() + na, zpos, sizeof(double) * nh);
-  std::memcpy(h.data() + na + nh, radii, sizeof(double) * nl);
+  std::vector<double> h(2 * (size_t)na + nh + nl);
+  for (int32_t a = 0; a < na; ++a) {  // cx[], then cy[]
+    h[a] = col_xy[2 * a];
+    h[na + a] = col_xy[2 * a + 1];
+  }
+  std::memcpy(h.data() + 2 * na, zpos, sizeof(double) * nh);
+  std::memcpy(h.data() + 2 * na + nh, radii, sizeof(double) * nl);
   hipError_t e = hipMemcpyAsync(p->d_geom, h.data(), sizeof(double) * h.size(),
                                 hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -117,13 +120,13 @@ Status create(const srt_grid *grid, double R, const double *angles, int32_t na,
   g.z0 = grid->z0;
   g.dxy = grid->dxy;
   g.dz = grid->dz;
-  g.R = R;
   g.na = na;
   g.nh = nh;
   g.nl = nl;
-  g.angles = p->d_geom;
-  g.zpos = p->d_geom + na;
-  g.radii = p->d_geom + na + nh;
+  g.cx = p->d_geom;
+  g.cy = p->d_geom + na;
+  g.zpos = p->d_geom + 2 * na;
+  g.radii = p->d_geom + 2 * na + nh;
 
   Coo pieces;
   auto free_pieces = [&]() {
@@ -206,8 +209,33 @@ srt_status srt_plan_create(const srt_grid *grid, double cyl_radius, const double
                            srt_dtype weight_dtype, srt_opmode mode, int32_t device,
                            void *hip_stream, srt_plan **out) {
   try {
-    return finish(create(grid, cyl_radius, angles, n_angles, z_pos, n_z, radii, n_radii,
-                         value_dtype, weight_dtype, mode, device, (hipStream_t)hip_stream, out));
+    if (out) *out = nullptr;
+    if (!angles) return finish(fail(SRT_EINVAL, "NULL argument"));
+    if (!std::isfinite(cyl_radius) || cyl_radius < 0)
+      return finish(fail(SRT_EINVAL, "cylinder radius must be finite and >= 0"));
+    if (n_angles <= 0) return finish(fail(SRT_EINVAL, "sample counts must be positive"));
+    if (!finite_all(angles, n_angles)) return finish(fail(SRT_EINVAL, "sample positions must be finite"));
+    // column a of the cylinder stands at (R cos angles[a], R sin angles[a])
+    std::vector<double> xy(2 * (size_t)n_angles);
+    for (int32_t a = 0; a < n_angles; ++a) {
+      xy[2 * a] = cyl_radius * std::cos(angles[a]);
+      xy[2 * a + 1] = cyl_radius * std::sin(angles[a]);
+    }
+    return finish(create(grid, xy.data(), n_angles, z_pos, n_z, radii, n_radii, value_dtype,
+                         weight_dtype, mode, device, (hipStream_t)hip_stream, out));
+  } catch (...) {
+    return finish(fail(SRT_ENOMEM, "host exception during plan creation"));
+  }
+}
+
+srt_status srt_plan_create_columns(const srt_grid *grid, const double *col_xy, int32_t n_cols,
+                                   const double *z_pos, int32_t n_z, const double *radii,
+                                   int32_t n_radii, srt_dtype value_dtype,
+                                   srt_dtype weight_dtype, srt_opmode mode, int32_t device,
+                                   void *hip_stream, srt_plan **out) {
+  try {
+    return finish(create(grid, col_xy, n_cols, z_pos, n_z, radii, n_radii, value_dtype,
+                         weight_dtype, mode, device, (hipStream_t)hip_stream, out));
   } catch (...) {
     return finish(fail(SRT_ENOMEM, "host exception during plan creation"));
   }

@@ -52,9 +52,9 @@ struct Csr {
 struct Geometry {
   int32_t ms = 0, mz = 0;
   double x0 = 0, z0 = 0, dxy = 0, dz = 0;
-  double R = 0;
   int32_t na = 0, nh = 0, nl = 0;
-  const double *angles = nullptr;  // device [na]
+  const double *cx = nullptr;      // device [na] column centre x
+  const double *cy = nullptr;      // device [na] column centre y
   const double *zpos = nullptr;    // device [nh]
   const double *radii = nullptr;   // device [nl]
 };

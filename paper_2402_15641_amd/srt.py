@@ -15,17 +15,20 @@ _TORCH = {"f32": torch.float32, "f64": torch.float64}
 
 
 class SRTPlan:
-    """Cylindrical-aperture SRT operator on one device.
+    """SRT operator for sensor columns parallel to z, on one device.
 
     Geometry: voxel (i, j, k) covers [x0 + i dxy, ...) x [x0 + j dxy, ...) x
     [z0 + k dz, ...); sensor column a sits at (R cos angles[a], R sin angles[a])
-    with heights z_pos and sphere radii `radii` (strictly increasing).
+    on a cylinder, or at col_xy[a] anywhere in the plane, with heights z_pos
+    and sphere radii `radii` (strictly increasing).
     Volumes are [B][mz][ms][ms]; data are [B][n_angles][n_z][n_radii].
     """
 
     def __init__(self, ms, mz, x0, z0, dxy, dz, cyl_radius, angles, z_pos, radii,
                  value_dtype: str = "f32", weight_dtype: str | None = None,
-                 device=None, mode: str = "auto"):
+                 device=None, mode: str = "auto", col_xy=None):
+        """col_xy (n x 2), when given, places the sensor columns at arbitrary
+        (x, y) positions; cyl_radius and angles are then ignored."""
         if weight_dtype is None:
             weight_dtype = value_dtype
         dev = torch.device("cuda", torch.cuda.current_device()) if device is None \
@@ -36,18 +39,26 @@ class SRTPlan:
         self.value_dtype, self.weight_dtype = value_dtype, weight_dtype
         self.dtype = _TORCH[value_dtype]
         self.ms, self.mz = int(ms), int(mz)
-        self.n_angles, self.n_z, self.n_radii = len(angles), len(z_pos), len(radii)
+        n_cols = len(angles) if col_xy is None else len(col_xy)
+        self.n_angles, self.n_z, self.n_radii = n_cols, len(z_pos), len(radii)
         with torch.cuda.device(dev):
-            self.handle = B.srt_plan_create(ms, mz, x0, z0, dxy, dz, cyl_radius, angles, z_pos,
-                                            radii, value_dtype, weight_dtype, mode,
-                                            dev.index or 0)
+            if col_xy is None:
+                self.handle = B.srt_plan_create(ms, mz, x0, z0, dxy, dz, cyl_radius, angles,
+                                                z_pos, radii, value_dtype, weight_dtype, mode,
+                                                dev.index or 0)
+            else:
+                self.handle = B.srt_plan_create_columns(ms, mz, x0, z0, dxy, dz, col_xy, z_pos,
+                                                        radii, value_dtype, weight_dtype, mode,
+                                                        dev.index or 0)
         self.info = B.srt_plan_get_info(self.handle)
 
     @classmethod
     def from_geometry(cls, g, **kw) -> "SRTPlan":
-        """From any object with ms, mz, x0, z0, dxy, dz, radius, angles, zpos, radii."""
+        """From any object with ms, mz, x0, z0, dxy, dz, radius, angles, zpos,
+        radii (and optionally centers: columns at arbitrary (x, y))."""
+        centers = getattr(g, "centers", None)
         return cls(g.ms, g.mz, g.x0, g.z0, g.dxy, g.dz, g.radius, g.angles, g.zpos, g.radii,
-                   **kw)
+                   col_xy=centers, **kw)
 
     @property
     def vol_shape(self):

@@ -36,6 +36,16 @@ class Aperture:
     angles: np.ndarray = field(repr=False)  # [N_a] radians
     zpos: np.ndarray = field(repr=False)  # [N_h]
     radii: np.ndarray = field(repr=False)  # [N_l], strictly increasing, > 0
+    # Columns anywhere in the (x, y) plane ([N_a][2]); None: on the cylinder
+    # at (R cos alpha_a, R sin alpha_a).
+    centers: np.ndarray | None = field(default=None, repr=False)
+
+    @property
+    def column_centers(self) -> np.ndarray:
+        """[N_a][2] (x, y) of every sensor column."""
+        if self.centers is not None:
+            return np.asarray(self.centers, dtype=np.float64)
+        return np.stack([self.radius * np.cos(self.angles), self.radius * np.sin(self.angles)], axis=1)
 
     @property
     def n_angles(self) -> int:
@@ -90,6 +100,24 @@ def cylinder_aperture(name: str, m: int, half_width: float, radius: float,
     return Aperture(name=name, ms=m, mz=mz, x0=-half_width, z0=-half_width,
                     dxy=h, dz=hz, radius=float(radius), angles=angles,
                     zpos=zpos, radii=radii)
+
+
+def column_aperture(name: str, m: int, half_width: float, centers, n_z: int, n_radii: int,
+                    l_max: float | None = None, mz: int | None = None) -> Aperture:
+    """Cubic grid [-W, W]^3 with sensor columns at arbitrary (x, y) positions
+    (each a line of N_h sensors parallel to z, Sec. 2), sharing the heights
+    and radii of a cylindrical aperture; l_max defaults to the largest
+    distance from a column to a grid corner."""
+    mz = m if mz is None else mz
+    c = np.asarray(centers, dtype=np.float64).reshape(-1, 2)
+    if l_max is None:
+        corners = np.array([[sx * half_width, sy * half_width] for sx in (-1, 1) for sy in (-1, 1)])
+        dxy = np.max(np.hypot(c[:, None, 0] - corners[None, :, 0], c[:, None, 1] - corners[None, :, 1]))
+        l_max = float(np.hypot(dxy, 2.0 * half_width))
+    ap = cylinder_aperture(name, m, half_width, 0.0, c.shape[0], n_z, n_radii, l_max=l_max, mz=mz)
+    return Aperture(name=name, ms=ap.ms, mz=ap.mz, x0=ap.x0, z0=ap.z0, dxy=ap.dxy, dz=ap.dz,
+                    radius=float("nan"), angles=np.arctan2(c[:, 1], c[:, 0]), zpos=ap.zpos,
+                    radii=ap.radii, centers=c)
 
 
 CONFIG_NAMES = ("grid32", "grid128", "pact256", "serve64", "serve128", "serve192")

@@ -80,3 +80,19 @@ def test_null_plan_calls():
     assert L.srt_cgls(None, None, None, 1, 1, None, None, 0, None) == B.SRT_EINVAL
     assert "plan" in B.srt_last_error()
     assert L.srt_cgls_workspace(None, 1, 1, ctypes.byref(r)) == B.SRT_EINVAL
+
+
+def test_create_columns_rejects_bad_positions():
+    L = B.lib()
+    grid = B.SrtGrid(8, 8, -1.0, -1.0, 0.25, 0.25)
+    zp = np.linspace(-1, 1, 3)
+    rad = np.linspace(0.1, 3.0, 8)
+    out = ctypes.c_void_p()
+    st = L.srt_plan_create_columns(ctypes.byref(grid), None, 2, zp.ctypes.data, 3,
+                                   rad.ctypes.data, 8, 0, 0, 0, 0, None, ctypes.byref(out))
+    assert st == B.SRT_EINVAL and "NULL" in B.srt_last_error()
+    xy = np.array([[1.5, 0.0], [np.inf, 0.2]])
+    st = L.srt_plan_create_columns(ctypes.byref(grid), xy.ctypes.data, 2, zp.ctypes.data, 3,
+                                   rad.ctypes.data, 8, 0, 0, 0, 0, None, ctypes.byref(out))
+    assert st == B.SRT_EINVAL and "finite" in B.srt_last_error()
+    assert out.value is None

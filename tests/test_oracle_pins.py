@@ -86,6 +86,22 @@ def test_a12_entries_match_sampling(seed):
             assert np.abs(bf - A[l]).max() <= 4 * spacing
 
 
+def test_a12_entries_match_sampling_for_arbitrary_columns():
+    """Columns anywhere in the plane (Sec. 2 needs only lines parallel to z):
+    inside the grid, on a grid line, on a pixel corner, far outside."""
+    from srt_inputs import column_aperture
+    centers = [(0.13, -0.41), (0.25, 0.6), (-0.5, -0.5), (2.7, -0.3), (-0.01, 1.9)]
+    ap = column_aperture("cols", 8, 1.0, centers, 2, 16, l_max=3.2)
+    a12s, _ = geo.assemble_all(ap)
+    n = 1 << 20
+    for A, c in zip(a12s, centers):
+        A = A.toarray()
+        for l in range(ap.n_radii):
+            bf = brute.sampled_a12_row(ap, c, ap.radii[l], n)
+            spacing = ap.radii[l] * 2 * np.pi / n
+            assert np.abs(bf - A[l]).max() <= 4 * spacing, (c, l)
+
+
 def test_a34_entries_match_sampling():
     """Every A34 entry equals the sampled half-circle arc length within the
     sampling bound; rho cells below the first midpoint receive nothing."""
