@@ -16,9 +16,12 @@ Contents (each function cites the passage of the paper it follows):
   cgls          least-squares reconstruction with the matched pair (conjugate
                 gradients on the normal equations), the use the paper gives
                 for an exactly matched adjoint
+  linear        both CRT matrices for a piecewise-linear (tent) voxel basis,
+                by exact arc splitting and Gauss-Legendre quadrature per piece
+                (Sec. 3.1: the method holds for other bases)
 
 Precision: float64 throughout. Every function here is pinned by a
 -m "not gpu" test against something other than itself (closed forms,
 brute-force sampling, invariants, symmetries); see tests/test_oracle_*.py.
 """
-from . import geometry, srt, closed_forms, brute, cgls  # noqa: F401
+from . import geometry, srt, closed_forms, brute, cgls, linear  # noqa: F401
