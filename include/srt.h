@@ -23,8 +23,10 @@
  *   - The rho axis of the intermediate image reuses the radii: cell l spans
  *     the midpoints between neighbouring radii (outer edges half a spacing
  *     beyond the end radii).
- *   - Weights are exact arc lengths computed in FP64 on the device and
- *     rounded once (round to nearest even) to the weight dtype.
+ *   - Weights are exact integrals of the basis functions along the arcs,
+ *     computed in FP64 on the device and rounded once (round to nearest
+ *     even) to the weight dtype: arc lengths for the piecewise-constant
+ *     basis, integrals of bilinear tents for the piecewise-linear one.
  *   - Every device pointer is owned by the caller; the plan owns its operator
  *     storage. All apply calls are asynchronous and ordered on the given HIP
  *     stream (NULL = the null stream).
@@ -60,6 +62,19 @@ typedef enum { SRT_F32 = 0, SRT_F64 = 1, SRT_BF16 = 2, SRT_F16 = 3 } srt_dtype;
  * AUTO picks STORED. */
 typedef enum { SRT_OP_AUTO = 0, SRT_OP_STORED = 1, SRT_OP_ONTHEFLY = 2 } srt_opmode;
 
+/* Voxel basis the operators discretise (Sec. 3.1 uses piecewise-constant
+ * voxels and notes that other bases, piecewise-linear ones among them, carry
+ * over).
+ * CONSTANT: f is constant on every voxel; intermediate images are constant on
+ *   rho cells that span the midpoints between neighbouring radii (outer edges
+ *   half a spacing beyond the end radii).
+ * LINEAR: f is the trilinear interpolant of its values at the voxel centres,
+ *   falling to zero half a voxel outside the grid; the intermediate image is
+ *   bilinear in (z, rho) between the z voxel centres and the radii, zero at
+ *   rho = 0 and one radius spacing past the last radius. Volumes then hold
+ *   nodal values at the voxel centres; layouts are unchanged. */
+typedef enum { SRT_BASIS_CONSTANT = 0, SRT_BASIS_LINEAR = 1 } srt_basis;
+
 typedef struct {
   int32_t ms;  /* voxels along x and along y */
   int32_t mz;  /* voxels along z */
@@ -77,8 +92,9 @@ typedef struct {
                              columns with l' >= live_radii are dropped because
                              the intermediate image is identically zero there */
   int32_t n_angles, n_z, n_radii;
-  double weight_scale_a12; /* stored weight = arc length * scale (power of 2) */
+  double weight_scale_a12; /* stored weight = exact weight * scale (power of 2) */
   double weight_scale_a34;
+  int32_t basis;           /* srt_basis of the plan */
 } srt_plan_info;
 
 /*
@@ -125,6 +141,25 @@ srt_status srt_plan_create_columns(const srt_grid *grid, const double *col_xy,
                                    srt_plan **out);
 
 /*
+ * srt_plan_create_basis -- as srt_plan_create / srt_plan_create_columns,
+ * with the voxel basis chosen (Sec. 3.1).
+ *   basis       SRT_BASIS_CONSTANT (what the two calls above build) or
+ *               SRT_BASIS_LINEAR
+ *   cyl_radius, angles   the cylinder aperture, used when col_xy is NULL
+ *   col_xy      host, n_cols (x, y) column positions, or NULL
+ *   n_cols      number of columns (angles or positions)
+ * Exactly one of angles and col_xy must be non-NULL. Other arguments,
+ * outputs and errors as srt_plan_create; an unknown basis is EINVAL.
+ */
+srt_status srt_plan_create_basis(const srt_grid *grid, srt_basis basis, double cyl_radius,
+                                 const double *angles, const double *col_xy, int32_t n_cols,
+                                 const double *z_pos, int32_t n_z,
+                                 const double *radii, int32_t n_radii,
+                                 srt_dtype value_dtype, srt_dtype weight_dtype,
+                                 srt_opmode mode, int32_t device, void *hip_stream,
+                                 srt_plan **out);
+
+/*
  * srt_forward -- Alg. 1 for every column and every batch item:
  * data[b][a][h][l] = sum over (l', k) of A34[(h,l),(l',k)] *
  *                    sum over p of A12_a[l', p] * vol[b][k][p].
@@ -165,7 +200,7 @@ srt_status srt_plan_get_info(const srt_plan *plan, srt_plan_info *info);
 
 /*
  * srt_plan_export_coo -- copy one stored operator to host memory as COO
- * triplets (row-major order) with weights converted back to arc lengths
+ * triplets (row-major order) with weights converted back to exact weights
  * (stored value / scale, as double). For tests.
  *   which     0 = A12 stacked (rows a*n_radii + l, cols j*ms + i),
  *             1 = A34 (rows h*n_radii + l, cols l'*mz + k),

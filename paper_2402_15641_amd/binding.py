@@ -19,9 +19,10 @@ SRT_OK, SRT_EINVAL, SRT_ENOMEM, SRT_EDEVICE, SRT_ENOTSUP = range(5)
 STATUS_NAMES = {0: "SRT_OK", 1: "SRT_EINVAL", 2: "SRT_ENOMEM", 3: "SRT_EDEVICE", 4: "SRT_ENOTSUP"}
 DTYPES = {"f32": 0, "f64": 1, "bf16": 2, "f16": 3}
 MODES = {"auto": 0, "stored": 1, "onthefly": 2}
+BASES = {"constant": 0, "linear": 1}
 
 # Every entry point declared in include/srt.h.
-SYMBOLS = ("srt_plan_create", "srt_plan_create_columns", "srt_forward", "srt_adjoint", "srt_plan_destroy",
+SYMBOLS = ("srt_plan_create", "srt_plan_create_columns", "srt_plan_create_basis", "srt_forward", "srt_adjoint", "srt_plan_destroy",
            "srt_plan_footprint", "srt_plan_get_info", "srt_plan_export_coo",
            "srt_plan_set_timing", "srt_plan_stage_times", "srt_cgls", "srt_cgls_workspace",
            "srt_last_error")
@@ -37,7 +38,8 @@ class SrtPlanInfo(ctypes.Structure):
     _fields_ = [("nnz_a12", ctypes.c_int64), ("nnz_a34", ctypes.c_int64),
                 ("live_radii", ctypes.c_int32), ("n_angles", ctypes.c_int32),
                 ("n_z", ctypes.c_int32), ("n_radii", ctypes.c_int32),
-                ("weight_scale_a12", ctypes.c_double), ("weight_scale_a34", ctypes.c_double)]
+                ("weight_scale_a12", ctypes.c_double), ("weight_scale_a34", ctypes.c_double),
+                ("basis", ctypes.c_int32)]
 
 
 class SRTError(RuntimeError):
@@ -65,6 +67,9 @@ def lib() -> ctypes.CDLL:
     L.srt_plan_create_columns.argtypes = [ctypes.POINTER(SrtGrid), P, I32, P, I32, P, I32,
                                           ctypes.c_int, ctypes.c_int, ctypes.c_int, I32, P,
                                           ctypes.POINTER(P)]
+    L.srt_plan_create_basis.argtypes = [ctypes.POINTER(SrtGrid), ctypes.c_int, D, P, P, I32, P,
+                                        I32, P, I32, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                        I32, P, ctypes.POINTER(P)]
     L.srt_forward.argtypes = [P, P, P, I32, P, SZ, P]
     L.srt_adjoint.argtypes = [P, P, P, I32, P, SZ, P]
     L.srt_plan_destroy.argtypes = [P]
@@ -137,6 +142,29 @@ def srt_plan_create_columns(ms, mz, x0, z0, dxy, dz, col_xy, z_pos, radii,
                                    int(device), _stream_ptr(stream) if stream is not False else None,
                                    ctypes.byref(out))
     _check(st, "srt_plan_create_columns")
+    return out.value
+
+
+def srt_plan_create_basis(ms, mz, x0, z0, dxy, dz, basis, z_pos, radii, cyl_radius=0.0,
+                          angles=None, col_xy=None, value_dtype="f32", weight_dtype="f32",
+                          mode="auto", device=0, stream=None) -> int:
+    """Builds a plan on the chosen voxel basis ("constant" or "linear") for a
+    cylinder aperture (cyl_radius, angles) or columns at col_xy (n x 2)."""
+    L = lib()
+    grid = SrtGrid(int(ms), int(mz), float(x0), float(z0), float(dxy), float(dz))
+    zp, rad = _f64(z_pos), _f64(radii)
+    ang = None if angles is None else _f64(angles)
+    xy = None if col_xy is None else np.ascontiguousarray(_f64(col_xy).reshape(-1, 2))
+    n = ang.size if ang is not None else (xy.shape[0] if xy is not None else 0)
+    out = ctypes.c_void_p()
+    st = L.srt_plan_create_basis(ctypes.byref(grid), BASES[basis], float(cyl_radius),
+                                 None if ang is None else ang.ctypes.data,
+                                 None if xy is None else xy.ctypes.data, n,
+                                 zp.ctypes.data, zp.size, rad.ctypes.data, rad.size,
+                                 DTYPES[value_dtype], DTYPES[weight_dtype], MODES[mode],
+                                 int(device), _stream_ptr(stream) if stream is not False else None,
+                                 ctypes.byref(out))
+    _check(st, "srt_plan_create_basis")
     return out.value
 
 

@@ -16,6 +16,15 @@
 // point. The piece's weight is radius * (angle difference). Pieces of one
 // cell cut apart by a quadrant boundary or revisited later are emitted
 // separately and summed when the matrix is assembled.
+//
+// Piecewise-linear basis (Sec. 3.1 allows other bases): the same walk runs
+// over the lattice of basis nodes instead of cell edges, and every piece
+// spreads its integral over the four corners of its lattice cell with the
+// exact integrals of the bilinear tents along the arc. Stage 1 nodes are the
+// voxel centres plus one virtual (zero) node half a voxel outside each end;
+// stage 2 nodes are the z voxel centres (virtual nodes likewise) times the
+// radii, with a zero node at rho = 0 and one a spacing past the last radius.
+// Entries at virtual nodes are not emitted.
 #include <hipcub/hipcub.hpp>
 
 #include "srt_internal.h"
@@ -34,6 +43,7 @@ struct UniformEdges {
   double x0, h;
   int n;
   __device__ double pos(int i) const { return x0 + h * (double)i; }
+  __device__ double width(int) const { return h; }
   // Number of edges at or below v.
   __device__ int count_le(double v) const {
     double f = floor((v - x0) / h);
@@ -79,6 +89,36 @@ struct RhoEdges {
   }
 };
 
+// Nodes of the linear basis along rho: 0, the radii, and the last radius
+// plus the last spacing (a single radius r gives 0, r, 2r); n = nl + 1 cells.
+struct RhoNodes {
+  const double *r;
+  int nl, n;
+  __device__ RhoNodes(const double *radii, int count) : r(radii), nl(count), n(count + 1) {}
+  __device__ double pos(int i) const {
+    if (i == 0) return 0.0;
+    if (i <= nl) return r[i - 1];
+    return r[nl - 1] + (nl > 1 ? r[nl - 1] - r[nl - 2] : r[0]);
+  }
+  __device__ double width(int i) const { return pos(i + 1) - pos(i); }
+  __device__ int count_le(double v) const {
+    int lo = 0, hi = n + 1;
+    while (lo < hi) {
+      int mid = (lo + hi) >> 1;
+      if (pos(mid) <= v) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+  }
+  __device__ int count_lt(double v) const {
+    int lo = 0, hi = n + 1;
+    while (lo < hi) {
+      int mid = (lo + hi) >> 1;
+      if (pos(mid) < v) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+  }
+};
+
 template <class E>
 __device__ int cell_of(const E &e, double v) {
   int i = e.count_le(v) - 1;
@@ -86,7 +126,8 @@ __device__ int cell_of(const E &e, double v) {
 }
 
 // Walks quadrants [0, nq) of the circle (cx + r cos t, cy + r sin t) over the
-// cell grid XE x YE and calls emit(ix, iy, length) for each piece inside it.
+// cell grid XE x YE and calls emit(ix, iy, t0, t1, cos tm, sin tm) for each
+// piece [t0, t1] inside cell (ix, iy), tm = (t0 + t1) / 2.
 template <class XE, class YE, class Emit>
 __device__ void walk_arc(double cx, double cy, double r, int nq, const XE &xe,
                          const YE &ye, Emit &emit) {
@@ -147,7 +188,7 @@ __device__ void walk_arc(double cx, double cy, double r, int nq, const XE &xe,
         sincos(tm, &s, &c);
         const int ix = cell_of(xe, cx + r * c);
         const int iy = cell_of(ye, cy + r * s);
-        if (ix >= 0 && iy >= 0) emit(ix, iy, r * (tn - tprev));
+        if (ix >= 0 && iy >= 0) emit(ix, iy, tprev, tn, c, s);
       }
       tprev = tn;
       if (last) break;
@@ -159,6 +200,7 @@ __device__ void walk_arc(double cx, double cy, double r, int nq, const XE &xe,
 // fill pass reproduces the count pass exactly). With keys == nullptr it only
 // counts; otherwise it writes at most `limit` entries and reports a mismatch.
 struct PieceEmit {
+  double r;
   uint64_t row_key;
   int64_t stride;      // column index = iy * stride + ix
   int live;            // iy >= live is dropped
@@ -166,13 +208,88 @@ struct PieceEmit {
   double *vals;
   int64_t limit;
   int64_t k = 0;
-  __device__ void operator()(int ix, int iy, double w) {
+  __device__ void operator()(int ix, int iy, double t0, double t1, double, double) {
     if (iy >= live) return;
     if (keys && k < limit) {
       keys[k] = row_key + (uint64_t)iy * (uint64_t)stride + (uint64_t)ix;
+      vals[k] = r * (t1 - t0);
+    }
+    ++k;
+  }
+};
+
+// sin(x) - x, without the cancellation of the direct form for small |x|:
+// below 1/2 the Taylor series through x^15 (truncation under 1e-17
+// relative), above it sin(x) - x directly (at most a factor 24 of
+// cancellation).
+__device__ double sin_minus_x(double x) {
+  if (fabs(x) >= 0.5) return sin(x) - x;
+  const double x2 = x * x;
+  double p = -1.0 / 1307674368000.0;  // -1/15!
+  p = p * x2 + 1.0 / 6227020800.0;    //  1/13!
+  p = p * x2 - 1.0 / 39916800.0;      // -1/11!
+  p = p * x2 + 1.0 / 362880.0;        //  1/9!
+  p = p * x2 - 1.0 / 5040.0;          // -1/7!
+  p = p * x2 + 1.0 / 120.0;           //  1/5!
+  p = p * x2 - 1.0 / 6.0;             // -1/3!
+  return p * x2 * x;
+}
+
+// Linear-basis emitter. A piece [t0, t1] in lattice cell (ix, iy) with
+// corners (X0, Y0) and sides (hx, hy) carries the bilinear weights
+// (1-u)(1-v), u(1-v), (1-u)v, uv with u = (cx + r cos t - X0) / hx and
+// v = (cy + r sin t - Y0) / hy; their integrals (measure r dt) follow in
+// closed form. Written about the mid-angle tm with d = t1 - t0, s = t - tm:
+//   u = um + (r/hx) (cos tm (cos s - 1) - sin tm sin s), and v likewise, so
+//   int u dt  = um d + A,   A = (r/hx) cos tm * 2 (sin(d/2) - d/2)
+//   int v dt  = vm d + B,   B = (r/hy) sin tm * 2 (sin(d/2) - d/2)
+//   int uv dt = um vm d + um B + vm A + C,
+//   C = r^2/(hx hy) sin tm cos tm ((sin d - d) - 4 (sin(d/2) - d/2))
+// (terms odd in s integrate to zero). The four weights sum to r d.
+// Lattice node (nx, ny) is emitted as column (ny - 1) * stride + (nx - 1)
+// when 1 <= nx <= nx_real and 1 <= ny <= ny_keep (virtual nodes and rho
+// nodes beyond `live` are dropped).
+template <class XE, class YE>
+struct LinearEmit {
+  const XE &xe;
+  const YE &ye;
+  double cx, cy, r;
+  uint64_t row_key;
+  int64_t stride;
+  int nx_real, ny_keep;
+  uint64_t *keys;
+  double *vals;
+  int64_t limit;
+  int64_t k = 0;
+  __device__ void put(int nx, int ny, double w) {
+    if (nx < 1 || nx > nx_real || ny < 1 || ny > ny_keep) return;
+    if (keys && k < limit) {
+      keys[k] = row_key + (uint64_t)(ny - 1) * (uint64_t)stride + (uint64_t)(nx - 1);
       vals[k] = w;
     }
     ++k;
+  }
+  __device__ void operator()(int ix, int iy, double t0, double t1, double c, double s) {
+    double w00 = 0.0, w10 = 0.0, w01 = 0.0, w11 = 0.0;
+    if (keys) {
+      const double hx = xe.width(ix), hy = ye.width(iy);
+      const double um = (cx + r * c - xe.pos(ix)) / hx;
+      const double vm = (cy + r * s - ye.pos(iy)) / hy;
+      const double d = t1 - t0;
+      const double e1 = 2.0 * sin_minus_x(0.5 * d);
+      const double A = (r / hx) * c * e1;
+      const double B = (r / hy) * s * e1;
+      const double C = (r / hx) * (r / hy) * s * c * (sin_minus_x(d) - 2.0 * e1);
+      const double uv = um * vm * d + um * B + vm * A + C;
+      w11 = r * uv;
+      w10 = r * (um * d + A - uv);
+      w01 = r * (vm * d + B - uv);
+      w00 = r * (d - um * d - A - vm * d - B + uv);
+    }
+    put(ix, iy, w00);
+    put(ix + 1, iy, w10);
+    put(ix, iy + 1, w01);
+    put(ix + 1, iy + 1, w11);
   }
 };
 
@@ -185,14 +302,26 @@ __global__ void a12_kernel(Geometry g, const int64_t *__restrict__ offs,
   if (row >= (int64_t)g.na * g.nl) return;
   const int a = (int)(row / g.nl), l = (int)(row % g.nl);
   const double cx = g.cx[a], cy = g.cy[a], r = g.radii[l];
-  const UniformEdges xe{g.x0, g.dxy, g.ms};
   const bool fill = counts == nullptr;
-  PieceEmit e{(uint64_t)row * (uint64_t)g.ms * (uint64_t)g.ms, g.ms, g.ms,
-              fill ? keys + offs[row] : nullptr, fill ? vals + offs[row] : nullptr,
-              fill ? offs[row + 1] - offs[row] : 0};
-  walk_arc(cx, cy, r, 4, xe, xe, e);
-  if (!fill) counts[row] = e.k;
-  else if (e.k != e.limit) atomicOr(mismatch, 1);
+  const uint64_t key = (uint64_t)row * (uint64_t)g.ms * (uint64_t)g.ms;
+  uint64_t *kp = fill ? keys + offs[row] : nullptr;
+  double *vp = fill ? vals + offs[row] : nullptr;
+  const int64_t lim = fill ? offs[row + 1] - offs[row] : 0;
+  int64_t k;
+  if (g.basis == SRT_BASIS_LINEAR) {
+    const UniformEdges xe{g.x0 - 0.5 * g.dxy, g.dxy, g.ms + 1};  // nodes 0 .. ms+1
+    LinearEmit<UniformEdges, UniformEdges> e{xe, xe, cx, cy, r, key, g.ms, g.ms, g.ms,
+                                             kp, vp, lim};
+    walk_arc(cx, cy, r, 4, xe, xe, e);
+    k = e.k;
+  } else {
+    const UniformEdges xe{g.x0, g.dxy, g.ms};
+    PieceEmit e{r, key, g.ms, g.ms, kp, vp, lim};
+    walk_arc(cx, cy, r, 4, xe, xe, e);
+    k = e.k;
+  }
+  if (!fill) counts[row] = k;
+  else if (k != lim) atomicOr(mismatch, 1);
 }
 
 // A34 row h*nl + l: upper half circle about (zpos[h], 0) over the (z, rho)
@@ -204,15 +333,28 @@ __global__ void a34_kernel(Geometry g, int live, const int64_t *__restrict__ off
   if (row >= (int64_t)g.nh * g.nl) return;
   const int h = (int)(row / g.nl), l = (int)(row % g.nl);
   const double cz = g.zpos[h], r = g.radii[l];
-  const UniformEdges ze{g.z0, g.dz, g.mz};
-  const RhoEdges re{g.radii, g.nl};
   const bool fill = counts == nullptr;
-  PieceEmit e{(uint64_t)row * (uint64_t)live * (uint64_t)g.mz, g.mz, live,
-              fill ? keys + offs[row] : nullptr, fill ? vals + offs[row] : nullptr,
-              fill ? offs[row + 1] - offs[row] : 0};
-  walk_arc(cz, 0.0, r, 2, ze, re, e);
-  if (!fill) counts[row] = e.k;
-  else if (e.k != e.limit) atomicOr(mismatch, 1);
+  const uint64_t key = (uint64_t)row * (uint64_t)live * (uint64_t)g.mz;
+  uint64_t *kp = fill ? keys + offs[row] : nullptr;
+  double *vp = fill ? vals + offs[row] : nullptr;
+  const int64_t lim = fill ? offs[row + 1] - offs[row] : 0;
+  int64_t k;
+  if (g.basis == SRT_BASIS_LINEAR) {
+    const UniformEdges ze{g.z0 - 0.5 * g.dz, g.dz, g.mz + 1};  // nodes 0 .. mz+1
+    const RhoNodes re(g.radii, g.nl);
+    LinearEmit<UniformEdges, RhoNodes> e{ze, re, cz, 0.0, r, key, g.mz, g.mz, live,
+                                         kp, vp, lim};
+    walk_arc(cz, 0.0, r, 2, ze, re, e);
+    k = e.k;
+  } else {
+    const UniformEdges ze{g.z0, g.dz, g.mz};
+    const RhoEdges re{g.radii, g.nl};
+    PieceEmit e{r, key, g.mz, live, kp, vp, lim};
+    walk_arc(cz, 0.0, r, 2, ze, re, e);
+    k = e.k;
+  }
+  if (!fill) counts[row] = k;
+  else if (k != lim) atomicOr(mismatch, 1);
 }
 
 // Count pass, exclusive scan, fill pass.

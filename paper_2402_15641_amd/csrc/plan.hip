@@ -26,7 +26,7 @@ struct DeviceGuard {
 };
 
 bool finite_all(const double *v, int64_t n) {
-  for (int32_t i = 0; i < n; ++i)
+  for (int64_t i = 0; i < n; ++i)
     if (!std::isfinite(v[i])) return false;
   return true;
 }
@@ -56,13 +56,15 @@ void destroy_contents(srt_plan *p) {
 }
 
 // col_xy: host [na][2] column centres (x, y).
-Status create(const srt_grid *grid, const double *col_xy, int32_t na,
+Status create(const srt_grid *grid, int32_t basis, const double *col_xy, int32_t na,
               const double *zpos, int32_t nh, const double *radii, int32_t nl,
               srt_dtype vdt, srt_dtype wdt, srt_opmode mode, int32_t device, hipStream_t s,
               srt_plan **out) {
   if (!out) return fail(SRT_EINVAL, "out is NULL");
   *out = nullptr;
   if (!grid || !col_xy || !zpos || !radii) return fail(SRT_EINVAL, "NULL argument");
+  if (basis != SRT_BASIS_CONSTANT && basis != SRT_BASIS_LINEAR)
+    return fail(SRT_EINVAL, "unknown basis");
   if (grid->ms <= 0 || grid->mz <= 0) return fail(SRT_EINVAL, "grid sizes must be positive");
   if (!(std::isfinite(grid->x0) && std::isfinite(grid->z0) && std::isfinite(grid->dxy) &&
         std::isfinite(grid->dz)) || grid->dxy <= 0 || grid->dz <= 0)
@@ -127,6 +129,7 @@ Status create(const srt_grid *grid, const double *col_xy, int32_t na,
   g.cy = p->d_geom + na;
   g.zpos = p->d_geom + 2 * na;
   g.radii = p->d_geom + 2 * na + nh;
+  g.basis = basis;
 
   Coo pieces;
   auto free_pieces = [&]() {
@@ -203,6 +206,25 @@ using namespace srt;
 
 extern "C" {
 
+namespace {
+// Column positions of a cylinder aperture: column a stands at
+// (R cos angles[a], R sin angles[a]).
+Status cylinder_columns(double cyl_radius, const double *angles, int32_t n_angles,
+                        std::vector<double> *xy) {
+  if (!angles) return fail(SRT_EINVAL, "NULL argument");
+  if (!std::isfinite(cyl_radius) || cyl_radius < 0)
+    return fail(SRT_EINVAL, "cylinder radius must be finite and >= 0");
+  if (n_angles <= 0) return fail(SRT_EINVAL, "sample counts must be positive");
+  if (!finite_all(angles, n_angles)) return fail(SRT_EINVAL, "sample positions must be finite");
+  xy->resize(2 * (size_t)n_angles);
+  for (int32_t a = 0; a < n_angles; ++a) {
+    (*xy)[2 * a] = cyl_radius * std::cos(angles[a]);
+    (*xy)[2 * a + 1] = cyl_radius * std::sin(angles[a]);
+  }
+  return Status{};
+}
+}  // namespace
+
 srt_status srt_plan_create(const srt_grid *grid, double cyl_radius, const double *angles,
                            int32_t n_angles, const double *z_pos, int32_t n_z,
                            const double *radii, int32_t n_radii, srt_dtype value_dtype,
@@ -210,19 +232,12 @@ srt_status srt_plan_create(const srt_grid *grid, double cyl_radius, const double
                            void *hip_stream, srt_plan **out) {
   try {
     if (out) *out = nullptr;
-    if (!angles) return finish(fail(SRT_EINVAL, "NULL argument"));
-    if (!std::isfinite(cyl_radius) || cyl_radius < 0)
-      return finish(fail(SRT_EINVAL, "cylinder radius must be finite and >= 0"));
-    if (n_angles <= 0) return finish(fail(SRT_EINVAL, "sample counts must be positive"));
-    if (!finite_all(angles, n_angles)) return finish(fail(SRT_EINVAL, "sample positions must be finite"));
-    // column a of the cylinder stands at (R cos angles[a], R sin angles[a])
-    std::vector<double> xy(2 * (size_t)n_angles);
-    for (int32_t a = 0; a < n_angles; ++a) {
-      xy[2 * a] = cyl_radius * std::cos(angles[a]);
-      xy[2 * a + 1] = cyl_radius * std::sin(angles[a]);
-    }
-    return finish(create(grid, xy.data(), n_angles, z_pos, n_z, radii, n_radii, value_dtype,
-                         weight_dtype, mode, device, (hipStream_t)hip_stream, out));
+    std::vector<double> xy;
+    Status st = cylinder_columns(cyl_radius, angles, n_angles, &xy);
+    if (!st.ok()) return finish(st);
+    return finish(create(grid, SRT_BASIS_CONSTANT, xy.data(), n_angles, z_pos, n_z, radii,
+                         n_radii, value_dtype, weight_dtype, mode, device,
+                         (hipStream_t)hip_stream, out));
   } catch (...) {
     return finish(fail(SRT_ENOMEM, "host exception during plan creation"));
   }
@@ -234,8 +249,33 @@ srt_status srt_plan_create_columns(const srt_grid *grid, const double *col_xy, i
                                    srt_dtype weight_dtype, srt_opmode mode, int32_t device,
                                    void *hip_stream, srt_plan **out) {
   try {
-    return finish(create(grid, col_xy, n_cols, z_pos, n_z, radii, n_radii, value_dtype,
-                         weight_dtype, mode, device, (hipStream_t)hip_stream, out));
+    return finish(create(grid, SRT_BASIS_CONSTANT, col_xy, n_cols, z_pos, n_z, radii, n_radii,
+                         value_dtype, weight_dtype, mode, device, (hipStream_t)hip_stream,
+                         out));
+  } catch (...) {
+    return finish(fail(SRT_ENOMEM, "host exception during plan creation"));
+  }
+}
+
+srt_status srt_plan_create_basis(const srt_grid *grid, srt_basis basis, double cyl_radius,
+                                 const double *angles, const double *col_xy, int32_t n_cols,
+                                 const double *z_pos, int32_t n_z, const double *radii,
+                                 int32_t n_radii, srt_dtype value_dtype,
+                                 srt_dtype weight_dtype, srt_opmode mode, int32_t device,
+                                 void *hip_stream, srt_plan **out) {
+  try {
+    if (out) *out = nullptr;
+    if ((angles == nullptr) == (col_xy == nullptr))
+      return finish(fail(SRT_EINVAL, "exactly one of angles and col_xy must be given"));
+    std::vector<double> xy;
+    if (angles) {
+      Status st = cylinder_columns(cyl_radius, angles, n_cols, &xy);
+      if (!st.ok()) return finish(st);
+      col_xy = xy.data();
+    }
+    return finish(create(grid, (int32_t)basis, col_xy, n_cols, z_pos, n_z, radii, n_radii,
+                         value_dtype, weight_dtype, mode, device, (hipStream_t)hip_stream,
+                         out));
   } catch (...) {
     return finish(fail(SRT_ENOMEM, "host exception during plan creation"));
   }
@@ -276,6 +316,7 @@ srt_status srt_plan_get_info(const srt_plan *plan, srt_plan_info *info) {
   info->n_radii = plan->geo.nl;
   info->weight_scale_a12 = plan->a12.scale;
   info->weight_scale_a34 = plan->a34.scale;
+  info->basis = plan->geo.basis;
   return SRT_OK;
 }
 

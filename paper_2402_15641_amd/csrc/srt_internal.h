@@ -57,6 +57,7 @@ struct Geometry {
   const double *cy = nullptr;      // device [na] column centre y
   const double *zpos = nullptr;    // device [nh]
   const double *radii = nullptr;   // device [nl]
+  int32_t basis = SRT_BASIS_CONSTANT;  // voxel basis the weights integrate
 };
 
 // Raw COO pieces of an operator: one entry per arc piece (duplicates allowed),

@@ -26,9 +26,11 @@ class SRTPlan:
 
     def __init__(self, ms, mz, x0, z0, dxy, dz, cyl_radius, angles, z_pos, radii,
                  value_dtype: str = "f32", weight_dtype: str | None = None,
-                 device=None, mode: str = "auto", col_xy=None):
+                 device=None, mode: str = "auto", col_xy=None, basis: str = "constant"):
         """col_xy (n x 2), when given, places the sensor columns at arbitrary
-        (x, y) positions; cyl_radius and angles are then ignored."""
+        (x, y) positions; cyl_radius and angles are then ignored. basis is
+        "constant" (piecewise-constant voxels) or "linear" (volumes hold
+        values at voxel centres, interpolated trilinearly)."""
         if weight_dtype is None:
             weight_dtype = value_dtype
         dev = torch.device("cuda", torch.cuda.current_device()) if device is None \
@@ -41,8 +43,15 @@ class SRTPlan:
         self.ms, self.mz = int(ms), int(mz)
         n_cols = len(angles) if col_xy is None else len(col_xy)
         self.n_angles, self.n_z, self.n_radii = n_cols, len(z_pos), len(radii)
+        self.basis = basis
         with torch.cuda.device(dev):
-            if col_xy is None:
+            if basis != "constant":
+                self.handle = B.srt_plan_create_basis(
+                    ms, mz, x0, z0, dxy, dz, basis, z_pos, radii, cyl_radius=cyl_radius,
+                    angles=angles if col_xy is None else None, col_xy=col_xy,
+                    value_dtype=value_dtype, weight_dtype=weight_dtype, mode=mode,
+                    device=dev.index or 0)
+            elif col_xy is None:
                 self.handle = B.srt_plan_create(ms, mz, x0, z0, dxy, dz, cyl_radius, angles,
                                                 z_pos, radii, value_dtype, weight_dtype, mode,
                                                 dev.index or 0)

@@ -96,3 +96,31 @@ def test_create_columns_rejects_bad_positions():
                                    rad.ctypes.data, 8, 0, 0, 0, 0, None, ctypes.byref(out))
     assert st == B.SRT_EINVAL and "finite" in B.srt_last_error()
     assert out.value is None
+
+
+def test_create_basis_rejects_bad_arguments():
+    L = B.lib()
+    grid = B.SrtGrid(8, 8, -1.0, -1.0, 0.25, 0.25)
+    zp = np.linspace(-1, 1, 3)
+    rad = np.linspace(0.1, 3.0, 8)
+    ang = np.linspace(0, 6, 4)
+    xy = np.array([[1.5, 0.0], [0.1, 0.2]])
+
+    def create(basis, angles, cols, n):
+        out = ctypes.c_void_p(12345)
+        st = L.srt_plan_create_basis(ctypes.byref(grid), basis, 1.5, angles, cols, n,
+                                     zp.ctypes.data, 3, rad.ctypes.data, 8, 0, 0, 0, 0, None,
+                                     ctypes.byref(out))
+        return st, out.value, B.srt_last_error()
+
+    st, out, msg = create(7, ang.ctypes.data, None, 4)
+    assert st == B.SRT_EINVAL and out is None and "basis" in msg
+    st, out, msg = create(1, ang.ctypes.data, xy.ctypes.data, 2)
+    assert st == B.SRT_EINVAL and out is None and "exactly one" in msg
+    st, out, msg = create(1, None, None, 2)
+    assert st == B.SRT_EINVAL and out is None and "exactly one" in msg
+    bad = np.array([0.0, np.nan])
+    st, out, msg = create(1, bad.ctypes.data, None, 2)
+    assert st == B.SRT_EINVAL and "finite" in msg
+    st, out, msg = create(1, None, xy.ctypes.data, 0)
+    assert st == B.SRT_EINVAL and "positive" in msg

@@ -1,0 +1,156 @@
+"""Piecewise-linear voxel basis on the device (srt_plan_create_basis) against
+the linear-basis oracle.
+
+Tolerances:
+  operator entries (FP64)   1e-12 * pitch per entry. Both sides integrate
+      the same tents along the same arcs exactly up to rounding (the oracle
+      by Gauss-Legendre quadrature per piece, the device in closed form), and
+      the weights are O(pitch).
+  forward / adjoint         relative L2 1e-12 (FP64), 1e-5 (FP32), as for the
+      piecewise-constant basis: the stage kernels are the same.
+  linear volume, end to end 1e-11 relative per sphere (FP64): the mean value
+      4 pi l^2 f(sensor) holds exactly for spheres inside the node hull.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import linear as lin, srt as osrt
+from srt_inputs import column_aperture, cylinder_aperture
+from oracle_cache import rel_l2, stacked
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm device")
+    from paper_2402_15641_amd import binding
+    binding.lib()
+
+
+def _plan(ap, value="f64", weight=None):
+    from paper_2402_15641_amd import SRTPlan
+    return SRTPlan.from_geometry(ap, value_dtype=value, weight_dtype=weight, basis="linear")
+
+
+def _t(x, dtype):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(device="cuda", dtype=dtype)
+
+
+def _np(t):
+    return t.detach().to("cpu", torch.float64).numpy()
+
+
+APERTURES = {
+    # cylinder around the grid, with ragged sizes (grid 27 x 27 x 19)
+    "cylinder": lambda: cylinder_aperture("lc", 27, 1.0, 1.4, 10, 7, 45, mz=19),
+    # columns inside the grid: on a voxel-centre line (a node line of the
+    # basis), on a voxel edge, at a generic point and outside
+    "columns": lambda: column_aperture("lk", 24, 1.0, [(1.0 / 24, -0.5 + 1.0 / 24), (0.0, 0.25),
+                                                       (0.13, -0.41), (1.7, 0.3)], 9, 40, mz=20),
+}
+_CACHE = {}
+
+
+def _operators(name):
+    if name not in _CACHE:
+        ap = APERTURES[name]()
+        _CACHE[name] = (ap,) + tuple(lin.assemble_all(ap))
+    return _CACHE[name]
+
+
+@pytest.mark.parametrize("name", sorted(APERTURES))
+def test_linear_operators_match_oracle(name):
+    ap, a12s, a34 = _operators(name)
+    plan = _plan(ap)
+    assert plan.info["basis"] == 1
+    h = ap.dxy
+    r, c, v = plan.export_coo(0)
+    A = sp.csr_matrix((v, (r, c)), shape=(ap.n_angles * ap.n_radii, ap.ms ** 2))
+    assert abs(A - stacked(a12s)).max() <= 1e-12 * h
+    live = plan.info["live_radii"]
+    rows_l = np.concatenate([m.tocoo().row for m in a12s])
+    assert rows_l.max() < live  # dropped rho nodes receive no stage-1 value
+    r, c, v = plan.export_coo(1)
+    B = sp.csr_matrix((v, (r, c)), shape=(ap.n_z * ap.n_radii, live * ap.mz))
+    assert abs(B - a34[:, :live * ap.mz]).max() <= 1e-12 * h
+    # stored transposes hold the same entries
+    r, c, v = plan.export_coo(2)
+    At = sp.csr_matrix((v, (r, c)), shape=(ap.ms ** 2, ap.n_angles * ap.n_radii))
+    assert abs(At - A.T).max() == 0.0
+    r, c, v = plan.export_coo(3)
+    Bt = sp.csr_matrix((v, (r, c)), shape=(live * ap.mz, ap.n_z * ap.n_radii))
+    assert abs(Bt - B.T).max() == 0.0
+
+
+@pytest.mark.parametrize("name", sorted(APERTURES))
+def test_linear_apply_matches_oracle(name):
+    ap, a12s, a34 = _operators(name)
+    rng = np.random.default_rng(61)
+    vols = rng.uniform(-1, 1, (3,) + ap.vol_shape)
+    data = rng.standard_normal((3,) + ap.data_shape)
+    fwd = np.stack([osrt.forward(v, a12s, a34, ap.n_z, ap.n_radii) for v in vols])
+    adj = np.stack([osrt.adjoint(g, a12s, a34, ap.ms, ap.mz) for g in data])
+    for value, tol in (("f64", 1e-12), ("f32", 1e-5)):
+        dt = torch.float64 if value == "f64" else torch.float32
+        p = _plan(ap, value)
+        assert rel_l2(_np(p.forward(_t(vols, dt))), fwd) <= tol
+        assert rel_l2(_np(p.adjoint(_t(data, dt))), adj) <= tol
+        # single item equals the batch's first item bitwise
+        assert torch.equal(p.forward(_t(vols[1], dt)), p.forward(_t(vols, dt))[1])
+
+
+def test_linear_volume_mean_value_end_to_end():
+    """A linear volume's sphere integrals are 4 pi l^2 f(sensor) for spheres
+    inside the node hull: pins the device path without the oracle."""
+    ap = column_aperture("mv", 32, 1.0, [(0.1, -0.05), (-0.15, 0.2), (0.0, 0.0)], 9, 48,
+                         l_max=1.2)
+    coef = (0.6, -0.9, 1.1, 0.35)
+    xs = ap.x0 + (np.arange(ap.ms) + 0.5) * ap.dxy
+    zs = ap.z0 + (np.arange(ap.mz) + 0.5) * ap.dz
+    F = coef[0] * xs[None, None, :] + coef[1] * xs[None, :, None] + coef[2] * zs[:, None, None] \
+        + coef[3]
+    Y = _np(_plan(ap).forward(_t(F, torch.float64)))
+    lo, hi = ap.x0 + ap.dxy / 2, ap.x0 + (ap.ms - 0.5) * ap.dxy
+    zlo, zhi = zs[0], zs[-1]
+    n = 0
+    for a, (cx, cy) in enumerate(ap.column_centers):
+        for h, zh in enumerate(ap.zpos):
+            for l, r in enumerate(ap.radii):
+                if (cx - r >= lo and cx + r <= hi and cy - r >= lo and cy + r <= hi
+                        and zh - r >= zlo and zh + r <= zhi):
+                    ref = 4 * np.pi * r * r * (coef[0] * cx + coef[1] * cy + coef[2] * zh
+                                               + coef[3])
+                    assert abs(Y[a, h, l] - ref) <= 1e-11 * max(1.0, abs(ref)), (a, h, l)
+                    n += 1
+    assert n >= 100
+
+
+def test_linear_adjoint_is_transpose():
+    ap = cylinder_aperture("ld", 40, 1.0, 1.3, 16, 12, 64, mz=33)
+    p = _plan(ap, "f32")
+    g = torch.Generator(device="cuda")
+    g.manual_seed(3)
+    f = torch.randn((2,) + ap.vol_shape, device="cuda", generator=g)
+    d = torch.randn((2,) + ap.data_shape, device="cuda", generator=g)
+    Af, Atd = p.forward(f).double(), p.adjoint(d).double()
+    lhs, rhs = float((Af * d.double()).sum()), float((f.double() * Atd).sum())
+    assert abs(lhs - rhs) <= 1e-6 * float(Af.norm()) * float(d.norm())
+
+
+def test_linear_cgls_runs_and_decreases():
+    """CGLS on the linear-basis pair: the data misfit decreases."""
+    ap = cylinder_aperture("lr", 24, 1.0, 1.4, 16, 12, 48, mz=24)
+    p = _plan(ap)
+    rng = np.random.default_rng(9)
+    F = _t(rng.uniform(0, 1, ap.vol_shape), torch.float64)
+    g = p.forward(F)
+    misfit = []
+    for k in (1, 3, 6):
+        f, _ = p.cgls(g, k)
+        misfit.append(float((p.forward(f) - g).norm()))
+    assert misfit[0] > misfit[1] > misfit[2]

@@ -10,6 +10,9 @@ things other than themselves:
     lies inside the node hull;
   * point sampling with bilinear weights (brute force) agrees entry by entry
     within the sampling error;
+  * end to end, a linear volume has sphere integrals 4 pi l^2 f(sensor)
+    (mean value over a sphere) for spheres inside the node hull, which pins
+    the hand-over from stage 1 to stage 2 (rho nodes, zero at rho = 0);
   * the composed operator is the constant-basis algorithm's structure: its
     adjoint is the transpose (dot test).
 """
@@ -122,6 +125,43 @@ def test_stage2_matches_bilinear_sampling():
             full = _sampled_lattice(zh, 0.0, r, ze, re, np.pi, n)
             bf = full[1:-1, 1:-1].reshape(-1)  # [l'][k], virtual nodes dropped
             assert np.abs(bf - A[h * ap.n_radii + l]).max() <= 8 * r * np.pi / n, (h, l)
+
+
+def linear_volume(ap, coef):
+    """Nodal values a x + b y + c z + d at the voxel centres, [k][j][i]."""
+    a, b, c, d = coef
+    xs = ap.x0 + (np.arange(ap.ms) + 0.5) * ap.dxy
+    zs = ap.z0 + (np.arange(ap.mz) + 0.5) * ap.dz
+    return (a * xs[None, None, :] + b * xs[None, :, None] + c * zs[:, None, None] + d)
+
+
+def spheres_inside_hull(ap):
+    """(a, h, l) of spheres that lie inside the node hull, with radii[l]
+    circles about the column inside the xy hull as well."""
+    lo, hi = ap.x0 + ap.dxy / 2, ap.x0 + (ap.ms - 0.5) * ap.dxy
+    zlo, zhi = ap.z0 + ap.dz / 2, ap.z0 + (ap.mz - 0.5) * ap.dz
+    out = []
+    for a, (cx, cy) in enumerate(ap.column_centers):
+        for h, zh in enumerate(ap.zpos):
+            for l, r in enumerate(ap.radii):
+                if (cx - r >= lo and cx + r <= hi and cy - r >= lo and cy + r <= hi
+                        and zh - r >= zlo and zh + r <= zhi):
+                    out.append((a, h, l))
+    return out
+
+
+def test_composed_exact_on_linear_volume():
+    ap = column_aperture("ex", 16, 1.0, [(0.1, -0.05), (-0.15, 0.2)], 9, 24, l_max=1.2)
+    coef = (0.6, -0.9, 1.1, 0.35)
+    a12s, a34 = lin.assemble_all(ap)
+    Y = srt.forward(linear_volume(ap, coef), a12s, a34, ap.n_z, ap.n_radii)
+    cases = spheres_inside_hull(ap)
+    assert len(cases) >= 20
+    for a, h, l in cases:
+        cx, cy = ap.column_centers[a]
+        r = ap.radii[l]
+        ref = 4 * np.pi * r * r * (coef[0] * cx + coef[1] * cy + coef[2] * ap.zpos[h] + coef[3])
+        assert abs(Y[a, h, l] - ref) <= 1e-12 * max(1.0, abs(ref)), (a, h, l)
 
 
 def test_linear_basis_dot_product():
