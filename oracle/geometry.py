@@ -13,8 +13,9 @@ and turns each CRT into a sparse matrix (Alg. 1 inputs):
                       (one matrix shared by all columns, N_h N_l x N_l M_z).
 
 Weights are exact arc lengths (radius times angle), computed from the sorted
-angles at which the circle crosses the cell edges: between two consecutive
-crossings the arc stays inside one cell, found from the arc's mid-angle.
+angles at which the circle crosses the cell edges or reaches an extreme in x
+or y: between two consecutive such angles the arc stays inside one cell,
+found from the arc's mid-angle.
 
 Readings of points the paper leaves open:
   * pixel index p = j * M_s + i (i along x); voxel k along z;
@@ -58,7 +59,10 @@ def arc_pieces(cx: float, cy: float, r: float, xe: np.ndarray, ye: np.ndarray,
     Returns (ix, iy, length): cell column, cell row and arc length of every
     piece whose mid-angle point lies inside the grid (duplicates not merged).
     """
-    ts = [np.array([0.0, t_end])]
+    # the arc's extremes in x and y are cuts as well: every piece is then
+    # monotone in both coordinates, and its mid-angle point lies strictly
+    # inside one cell even where the arc touches a cell edge tangentially
+    ts = [np.array([0.0, t_end]), 0.5 * np.pi * np.arange(5)]
     u = (xe - cx) / r
     u = u[np.abs(u) < 1.0]
     a = np.arccos(u)  # crossings with x = const: cos t = u

@@ -102,6 +102,26 @@ def test_a12_entries_match_sampling_for_arbitrary_columns():
             assert np.abs(bf - A[l]).max() <= 4 * spacing, (c, l)
 
 
+def test_a12_entries_match_sampling_for_tangent_circles():
+    """Degenerate placements: a column on a voxel-centre line or a grid line,
+    with radii that are multiples of the pitch, so that circles touch grid
+    lines tangentially with the crossings placed symmetrically about the
+    touching point."""
+    from srt_inputs import column_aperture
+    h = 0.25
+    centers = [(h / 2, 0.0), (0.0, h / 2), (h / 2, h / 2), (0.0, 0.0)]
+    ap = column_aperture("tan", 8, 1.0, centers, 2, 6, l_max=1.5)
+    assert np.allclose(ap.radii / h, np.round(ap.radii / h))
+    a12s, _ = geo.assemble_all(ap)
+    n = 1 << 20
+    for A, c in zip(a12s, centers):
+        A = A.toarray()
+        for l in range(ap.n_radii):
+            bf = brute.sampled_a12_row(ap, c, ap.radii[l], n)
+            spacing = ap.radii[l] * 2 * np.pi / n
+            assert np.abs(bf - A[l]).max() <= 4 * spacing, (c, l)
+
+
 def test_a34_entries_match_sampling():
     """Every A34 entry equals the sampled half-circle arc length within the
     sampling bound; rho cells below the first midpoint receive nothing."""
