@@ -88,7 +88,7 @@ def cpu_baseline(ap, F64, n_cols=32, h_stride=8):
         t1 += time.perf_counter() - s
         s = time.perf_counter()
         Y = osrt.stage2(a34, G, ap.n_z, ap.n_radii)
-        Gp = osrt.adj_stage2(a34, Y, ap.n_radii, ap.mz)
+        Gp = osrt.adj_stage2(a34, Y, ap.mz)
         t2 += time.perf_counter() - s
         s = time.perf_counter()
         osrt.adj_stage1(A, Gp, ap.ms)

@@ -40,18 +40,19 @@ def sampled_a12_row(ap, center, radius, n):
 
 
 def sampled_a34_row(ap, zc, radius, n):
-    """Dense sampled row of A34 (length N_l M_z)."""
+    """Dense sampled row of A34 (length N_rho M_z)."""
     ze = grid_edges(ap.z0, ap.dz, ap.mz)
-    re = rho_edges(ap.radii)
+    re = rho_edges(ap.rho_grid)
     ik, il, w = sampled_arc(zc, 0.0, radius, ze, re, n, np.pi)
-    return np.bincount(il * ap.mz + ik, weights=w, minlength=ap.n_radii * ap.mz)
+    return np.bincount(il * ap.mz + ik, weights=w, minlength=ap.n_rho * ap.mz)
 
 
 def sampled_forward(F, ap, n1, n2, angles_idx=None):
     """Alg. 1 with both circular transforms replaced by point sampling.
 
-    Stage 1: for every column a, radius l' and slice k, sum F over n1
-    equispaced points of the circle of radius l_l' about the column centre.
+    Stage 1: for every column a, stage-2 radius rho_l' and slice k, sum F over
+    n1 equispaced points of the circle of radius rho_l' about the column
+    centre.
     Stage 2: for every height h and radius l, sum the stage-1 image over n2
     equispaced points of the half circle about (z_h, 0), each point taking the
     value of the (rho cell, z slice) that contains it.
@@ -59,14 +60,15 @@ def sampled_forward(F, ap, n1, n2, angles_idx=None):
     angles_idx = range(ap.n_angles) if angles_idx is None else angles_idx
     xe = grid_edges(ap.x0, ap.dxy, ap.ms)
     ze = grid_edges(ap.z0, ap.dz, ap.mz)
-    re = rho_edges(ap.radii)
+    rgrid = ap.rho_grid
+    re = rho_edges(rgrid)
     Fp = F.reshape(ap.mz, -1)  # [k][p]
     out = []
     t2 = np.pi * (np.arange(n2) + 0.5) / n2
     for a in angles_idx:
-        cx, cy = ap.radius * np.cos(ap.angles[a]), ap.radius * np.sin(ap.angles[a])
-        G = np.zeros((ap.n_radii, ap.mz))
-        for lp, rad in enumerate(ap.radii):
+        cx, cy = ap.column_centers[a]
+        G = np.zeros((rgrid.size, ap.mz))
+        for lp, rad in enumerate(rgrid):
             ix, iy, w = sampled_arc(cx, cy, rad, xe, xe, n1)
             if ix.size:
                 G[lp] = (Fp[:, iy * ap.ms + ix] * w[None, :]).sum(axis=1)
@@ -76,8 +78,8 @@ def sampled_forward(F, ap, n1, n2, angles_idx=None):
             rho = ap.radii[:, None] * np.sin(t2)[None, :]
             k = np.searchsorted(ze, z, side="right") - 1
             lp = np.searchsorted(re, rho, side="right") - 1
-            ok = (k >= 0) & (k < ap.mz) & (lp >= 0) & (lp < ap.n_radii)
-            vals = np.where(ok, G[np.clip(lp, 0, ap.n_radii - 1), np.clip(k, 0, ap.mz - 1)], 0.0)
+            ok = (k >= 0) & (k < ap.mz) & (lp >= 0) & (lp < rgrid.size)
+            vals = np.where(ok, G[np.clip(lp, 0, rgrid.size - 1), np.clip(k, 0, ap.mz - 1)], 0.0)
             Y[h] = vals.sum(axis=1) * ap.radii * np.pi / n2
         out.append(Y)
     return np.stack(out)

@@ -23,6 +23,10 @@ Readings of points the paper leaves open:
     midpoints between neighbouring radii, the outer edges being half a
     spacing beyond the first and last radius (for l_l = l dl the cells are
     [(l'-1/2) dl, (l'+1/2) dl]);
+  * that axis may also be a grid of its own, rho_0 < ... < rho_{N_rho - 1}
+    (ap.rho_grid): stage 1 then evaluates the circle transform at the rho_m
+    (A12 is N_rho x M_s^2) and the cells are built from the rho_m in the same
+    way (A34 is N_h N_l x N_rho M_z); without one, rho_m = l_m;
   * row (h, l) of A34 has index h N_l + l, column (l', k) has index l' M_z + k;
   * pieces of zero length are dropped; several pieces of one circle in one
     cell are summed.
@@ -94,7 +98,7 @@ def a12_row(ap, center, radius: float):
 
 def assemble_a12(ap, angle: float, rows=None) -> sp.csr_matrix:
     """A12 for the sensor column at angle `angle` on the cylinder (Alg. 1
-    input, N_l x M_s^2). `rows` restricts assembly to a subset of radius
+    input, N_rho x M_s^2). `rows` restricts assembly to a subset of radius
     indices (others empty)."""
     return assemble_a12_at(ap, (ap.radius * np.cos(angle), ap.radius * np.sin(angle)), rows)
 
@@ -102,22 +106,23 @@ def assemble_a12(ap, angle: float, rows=None) -> sp.csr_matrix:
 def assemble_a12_at(ap, c, rows=None) -> sp.csr_matrix:
     """A12 for the sensor column through (x, y) = c: Sec. 2 only needs the
     sensors of a group on one line parallel to z, wherever that line is."""
-    rows = range(ap.n_radii) if rows is None else rows
+    rho = ap.rho_grid
+    rows = range(rho.size) if rows is None else rows
     ri, ci, vi = [], [], []
     for l in rows:
-        cols, w = a12_row(ap, c, ap.radii[l])
+        cols, w = a12_row(ap, c, rho[l])
         ri.append(np.full(cols.size, l))
         ci.append(cols)
         vi.append(w)
     ri, ci, vi = (np.concatenate(x) if x else np.zeros(0) for x in (ri, ci, vi))
     return sp.csr_matrix((vi, (ri.astype(np.int64), ci.astype(np.int64))),
-                         shape=(ap.n_radii, ap.ms * ap.ms))
+                         shape=(rho.size, ap.ms * ap.ms))
 
 
 def a34_row(ap, zc: float, radius: float):
     """Row of A34 for one half circle centred (z = zc, rho = 0): (cols, lengths)."""
     ze = grid_edges(ap.z0, ap.dz, ap.mz)
-    re = rho_edges(ap.radii)
+    re = rho_edges(ap.rho_grid)
     ik, il, w = arc_pieces(zc, 0.0, radius, ze, re, np.pi)
     col = il * ap.mz + ik
     cols, inv = np.unique(col, return_inverse=True)
@@ -125,7 +130,7 @@ def a34_row(ap, zc: float, radius: float):
 
 
 def assemble_a34(ap, heights=None) -> sp.csr_matrix:
-    """A34 (Alg. 1 input, N_h N_l x N_l M_z), shared by every sensor column.
+    """A34 (Alg. 1 input, N_h N_l x N_rho M_z), shared by every sensor column.
     `heights` restricts assembly to a subset of sensor-height indices."""
     heights = range(ap.n_z) if heights is None else heights
     ri, ci, vi = [], [], []
@@ -137,7 +142,7 @@ def assemble_a34(ap, heights=None) -> sp.csr_matrix:
             vi.append(w)
     ri, ci, vi = (np.concatenate(x) if x else np.zeros(0) for x in (ri, ci, vi))
     return sp.csr_matrix((vi, (ri.astype(np.int64), ci.astype(np.int64))),
-                         shape=(ap.n_z * ap.n_radii, ap.n_radii * ap.mz))
+                         shape=(ap.n_z * ap.n_radii, ap.n_rho * ap.mz))
 
 
 def assemble_all(ap):

@@ -14,9 +14,10 @@ readings taken here:
     interpolant: A12[l, (i, j)] = integral over the circle of L_i(x) L_j(y)
     (measure rho dphi); the z dependence stays the coefficient of L_k(z);
   * stage 2 represents f12(z, rho) by tents in z (the same L_k) times tents
-    in rho centred on the radii, with a node of value zero at rho = 0 (the
-    circle transform vanishes there) and one past the last radius at the
-    last spacing: A34[(h, l), (l', k)] = integral over the upper half circle
+    in rho centred on the radii (or on the stage-2 radial grid when the
+    aperture has one), with a node of value zero at rho = 0 (the circle
+    transform vanishes there) and one past the last radius at the last
+    spacing: A34[(h, l), (l', k)] = integral over the upper half circle
     about (z_h, 0) of L_k(z) T_l'(rho) (measure l dtheta).
 
 Each arc is cut at the lines through the nodes, where the interpolant's
@@ -104,22 +105,23 @@ def a12_row(ap, center, radius: float):
 def assemble_a12_at(ap, c) -> sp.csr_matrix:
     """Linear-basis A12 for the column through (x, y) = c (N_l x M_s^2)."""
     ri, ci, vi = [], [], []
-    for l in range(ap.n_radii):
-        cols, w = a12_row(ap, c, ap.radii[l])
+    rho = ap.rho_grid
+    for l in range(rho.size):
+        cols, w = a12_row(ap, c, rho[l])
         ri.append(np.full(cols.size, l))
         ci.append(cols)
         vi.append(w)
     ri, ci, vi = (np.concatenate(x) for x in (ri, ci, vi))
     return sp.csr_matrix((vi, (ri.astype(np.int64), ci.astype(np.int64))),
-                         shape=(ap.n_radii, ap.ms * ap.ms))
+                         shape=(rho.size, ap.ms * ap.ms))
 
 
 def a34_row(ap, zc: float, radius: float):
     """Row of the linear-basis A34: (cols l' * M_z + k, weights)."""
     ze = node_edges(ap.z0, ap.dz, ap.mz)
-    re = rho_nodes(ap.radii)
+    re = rho_nodes(ap.rho_grid)
     nk, nl, w = arc_corner_weights(zc, 0.0, radius, ze, re, np.pi)
-    ok = (nk >= 1) & (nk <= ap.mz) & (nl >= 1) & (nl <= ap.n_radii)
+    ok = (nk >= 1) & (nk <= ap.mz) & (nl >= 1) & (nl <= ap.n_rho)
     col = (nl[ok] - 1) * ap.mz + (nk[ok] - 1)
     cols, inv = np.unique(col, return_inverse=True)
     return cols, np.bincount(inv, weights=w[ok], minlength=cols.size)
@@ -136,7 +138,7 @@ def assemble_a34(ap, heights=None) -> sp.csr_matrix:
             vi.append(w)
     ri, ci, vi = (np.concatenate(x) for x in (ri, ci, vi))
     return sp.csr_matrix((vi, (ri.astype(np.int64), ci.astype(np.int64))),
-                         shape=(ap.n_z * ap.n_radii, ap.n_radii * ap.mz))
+                         shape=(ap.n_z * ap.n_radii, ap.n_rho * ap.mz))
 
 
 def assemble_all(ap):

@@ -15,15 +15,15 @@ import numpy as np
 
 def stage1(a12, F: np.ndarray) -> np.ndarray:
     """Alg. 1, first product: reshape F to M_s^2 x M_z (pixel by slice) and
-    apply the circle transform in every slice: G = A12 F, N_l x M_z."""
+    apply the circle transform in every slice: G = A12 F, N_rho x M_z."""
     mz = F.shape[0]
     F2 = F.reshape(mz, -1).T
     return np.asarray(a12 @ F2)
 
 
 def stage2(a34, G: np.ndarray, n_z: int, n_radii: int) -> np.ndarray:
-    """Alg. 1, second product: flatten G to a vector of length N_l M_z, apply
-    the half-circle transform and reshape to N_h x N_l."""
+    """Alg. 1, second product: flatten G to a vector of length N_rho M_z,
+    apply the half-circle transform and reshape to N_h x N_l."""
     return np.asarray(a34 @ G.reshape(-1)).reshape(n_z, n_radii)
 
 
@@ -37,9 +37,10 @@ def forward(F: np.ndarray, a12s, a34, n_z: int, n_radii: int) -> np.ndarray:
     return np.stack([column_srt(F, a, a34, n_z, n_radii) for a in a12s])
 
 
-def adj_stage2(a34, Y_a: np.ndarray, n_radii: int, mz: int) -> np.ndarray:
-    """Alg. 2, first product: G' = (A34)^T y, reshaped to N_l x M_z."""
-    return np.asarray(a34.T @ Y_a.reshape(-1)).reshape(n_radii, mz)
+def adj_stage2(a34, Y_a: np.ndarray, mz: int) -> np.ndarray:
+    """Alg. 2, first product: G' = (A34)^T y, reshaped to N_rho x M_z (the
+    radial axis of the stage-2 image; N_rho = N_l unless it has its own)."""
+    return np.asarray(a34.T @ Y_a.reshape(-1)).reshape(-1, mz)
 
 
 def adj_stage1(a12, Gp: np.ndarray, ms: int) -> np.ndarray:
@@ -50,7 +51,7 @@ def adj_stage1(a12, Gp: np.ndarray, ms: int) -> np.ndarray:
 
 def column_adjoint(Y_a: np.ndarray, a12, a34, ms: int, mz: int) -> np.ndarray:
     """Alg. 2 (AdjColumnSRT) for one sensor column."""
-    return adj_stage1(a12, adj_stage2(a34, Y_a, Y_a.shape[1], mz), ms)
+    return adj_stage1(a12, adj_stage2(a34, Y_a, mz), ms)
 
 
 def adjoint(Y: np.ndarray, a12s, a34, ms: int, mz: int) -> np.ndarray:

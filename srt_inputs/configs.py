@@ -16,7 +16,7 @@ Readings of what the paper leaves open (all stated once here):
 """
 from __future__ import annotations
 
-from dataclasses import dataclass, field
+from dataclasses import dataclass, field, replace
 
 import numpy as np
 
@@ -39,6 +39,18 @@ class Aperture:
     # Columns anywhere in the (x, y) plane ([N_a][2]); None: on the cylinder
     # at (R cos alpha_a, R sin alpha_a).
     centers: np.ndarray | None = field(default=None, repr=False)
+    # Radial grid of the stage-2 image ([N_rho], strictly increasing, > 0);
+    # None: the sphere radii themselves (the paper's choice).
+    rho: np.ndarray | None = field(default=None, repr=False)
+
+    @property
+    def rho_grid(self) -> np.ndarray:
+        """[N_rho] radii at which stage 1 evaluates the circle transform."""
+        return np.asarray(self.radii if self.rho is None else self.rho, dtype=np.float64)
+
+    @property
+    def n_rho(self) -> int:
+        return int(self.rho_grid.size)
 
     @property
     def column_centers(self) -> np.ndarray:
@@ -100,6 +112,15 @@ def cylinder_aperture(name: str, m: int, half_width: float, radius: float,
     return Aperture(name=name, ms=m, mz=mz, x0=-half_width, z0=-half_width,
                     dxy=h, dz=hz, radius=float(radius), angles=angles,
                     zpos=zpos, radii=radii)
+
+
+def with_rho_grid(ap: Aperture, n_rho: int, rho_max: float | None = None) -> Aperture:
+    """The same aperture with a stage-2 radial grid of its own: N_rho uniform
+    values rho_m = m * rho_max / N_rho, m = 1..N_rho (rho_max defaults to the
+    largest sphere radius)."""
+    rho_max = float(ap.radii[-1]) if rho_max is None else float(rho_max)
+    rho = rho_max * np.arange(1, n_rho + 1, dtype=np.float64) / n_rho
+    return replace(ap, name=f"{ap.name}_rho{n_rho}", rho=rho)
 
 
 def column_aperture(name: str, m: int, half_width: float, centers, n_z: int, n_radii: int,

@@ -52,6 +52,10 @@ APERTURES = {
     # basis), on a voxel edge, at a generic point and outside
     "columns": lambda: column_aperture("lk", 24, 1.0, [(1.0 / 24, -0.5 + 1.0 / 24), (0.0, 0.25),
                                                        (0.13, -0.41), (1.7, 0.3)], 9, 40, mz=20),
+    # circles tangent to node lines with symmetric crossings: columns on a
+    # grid line and a node line, radii multiples of the pitch
+    "tangent": lambda: column_aperture("lt", 16, 1.0, [(0.0, 0.0625), (0.0625, 0.0),
+                                                       (0.0, 0.0)], 9, 24, l_max=3.0),
 }
 _CACHE = {}
 

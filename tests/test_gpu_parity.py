@@ -222,7 +222,7 @@ def test_pact256_sampled_forward_and_sparse_adjoint():
     a34s = geo.assemble_a34(ap, heights=sel_h)
     ref = np.zeros(ap.vol_shape)
     for a in sel_a:
-        Gp = osrt.adj_stage2(a34s, din[a], ap.n_radii, ap.mz)
+        Gp = osrt.adj_stage2(a34s, din[a], ap.mz)
         ref += osrt.adj_stage1(geo.assemble_a12(ap, ap.angles[a]), Gp, ap.ms)
     assert rel_l2(Fp, ref) <= 1e-5
 
@@ -249,6 +249,27 @@ def test_pact256_batch_over_4gib_matches_single():
     assert torch.equal(Fpb[0], Fp1) and torch.equal(Fpb[-1], Fp1)
     # the scaled items are scaled copies up to FP32 rounding
     assert rel_l2(_np(Yb[4]), 2.0 * _np(Y1)) <= 1e-6
+
+
+# ------------------------------------------------------------------ tangent circles
+def test_tangent_circles_match_oracle():
+    """Circles that touch grid lines tangentially, with the edge crossings
+    symmetric about the touching point (columns on voxel-centre and grid
+    lines, radii multiples of the pitch): FP64 operator entries."""
+    from srt_inputs import column_aperture
+    h = 0.125
+    centers = [(h / 2, 0.0), (0.0, h / 2), (h / 2, h / 2), (0.0, 0.0), (1.5, 0.0)]
+    ap = column_aperture("tan", 16, 1.0, centers, 9, 24, l_max=3.0)
+    assert np.allclose(ap.radii / h, np.round(ap.radii / h))
+    a12s, a34 = geo.assemble_all(ap)
+    plan = _plan(ap, "f64")
+    r, c, v = plan.export_coo(0)
+    A = sp.csr_matrix((v, (r, c)), shape=(ap.n_angles * ap.n_radii, ap.ms ** 2))
+    assert abs(A - stacked(a12s)).max() <= 1e-12 * h
+    live = plan.info["live_radii"]
+    r, c, v = plan.export_coo(1)
+    B = sp.csr_matrix((v, (r, c)), shape=(ap.n_z * ap.n_radii, live * ap.mz))
+    assert abs(B - a34[:, :live * ap.mz]).max() <= 1e-12 * h
 
 
 # ------------------------------------------------------------------ columns anywhere
