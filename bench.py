@@ -20,6 +20,12 @@ Prints one JSON line on stdout. Besides throughput it reports:
                 same workload and scaled to one pair
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--weights f32|bf16|f16]
+                    [--basis constant|linear] [--n-rho N]
+
+--basis linear and --n-rho N (a stage-2 radial grid of N values instead of the
+radii) measure the same workload on the widened operators; those runs report
+no cpu_baseline (the linear-basis oracle takes hours at this size) and no
+traffic (the counters were taken on the default operators).
 """
 from __future__ import annotations
 
@@ -109,6 +115,9 @@ def main():
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--weights", default="f32", choices=["f32", "bf16", "f16"])
     p.add_argument("--workload", default="pact256", choices=["pact256", "grid128"])
+    p.add_argument("--basis", default="constant", choices=["constant", "linear"])
+    p.add_argument("--n-rho", type=int, default=0,
+                   help="stage-2 radial grid of this many values (0: the radii)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--profile-copy", action="store_true",
                    help="also run one 1 GiB read + 1 GiB write kernel (torch.neg; counter "
@@ -120,21 +129,25 @@ def main():
         sys.exit(2)
 
     import torch
-    from srt_inputs import config, phantoms
+    from srt_inputs import config, phantoms, with_rho_grid
     from paper_2402_15641_amd import SRTPlan, binding as B
 
     if not torch.cuda.is_available():
         log("bench.py needs a ROCm device")
         sys.exit(1)
+    variant = args.basis != "constant" or args.n_rho > 0
     ap = config(args.workload)
     t0 = time.perf_counter()
     F64 = phantoms.phantom(ap)
+    if args.n_rho > 0:
+        ap = with_rho_grid(ap, args.n_rho)
     log(f"phantom {time.perf_counter() - t0:.1f} s")
     vol = torch.from_numpy(F64).float().cuda()
     F_in = vol.double().cpu().numpy()
 
     t0 = time.perf_counter()
-    plan = SRTPlan.from_geometry(ap, value_dtype="f32", weight_dtype=args.weights)
+    plan = SRTPlan.from_geometry(ap, value_dtype="f32", weight_dtype=args.weights,
+                                 basis=args.basis)
     torch.cuda.synchronize()
     t_plan = time.perf_counter() - t0
     info = plan.info
@@ -184,7 +197,7 @@ def main():
     dom = max(stages, key=lambda k: stages[k][0])
     dom_ms, dom_flop = stages[dom]
     achieved = dom_flop / (dom_ms * 1e-3) / 1e12
-    traffic = measured_traffic(dom, 1)
+    traffic = None if variant else measured_traffic(dom, 1)
 
     wb = {"f32": 4, "bf16": 2, "f16": 2}[args.weights]
     op_bytes = 2 * (nnz12 + nnz34) * (4 + wb)  # operator and its transpose, once each
@@ -209,6 +222,7 @@ def main():
                                                         if args.workload == "pact256" else
                                                         "128^3 on [-1,1]^3, R=1.3, 128 x 128 x 512"),
                    "batch": 1, "weights": args.weights, "phantom": "seeded",
+                   "basis": args.basis, "n_rho": info["n_rho"],
                    "nnz_a12": nnz12, "nnz_a34": nnz34, "plan_build_s": round(t_plan, 3)},
         "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved,
                      "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
@@ -218,7 +232,7 @@ def main():
                 "peak_gbps": PEAK_HBM_GBPS, "frac": hbm_gbps / PEAK_HBM_GBPS},
         "stage_ms": {"forward": fwd_ms, "adjoint": adj_ms},
     }
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not variant:
         t0 = time.perf_counter()
         result["cpu_baseline"] = cpu_baseline(ap, F_in)
         log(f"cpu baseline {time.perf_counter() - t0:.1f} s")

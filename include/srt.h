@@ -22,7 +22,7 @@
  *     x [z0 + k dz, z0 + (k+1) dz].
  *   - The rho axis of the intermediate image reuses the radii: cell l spans
  *     the midpoints between neighbouring radii (outer edges half a spacing
- *     beyond the end radii).
+ *     beyond the end radii), unless srt_plan_desc gives it a grid of its own.
  *   - Weights are exact integrals of the basis functions along the arcs,
  *     computed in FP64 on the device and rounded once (round to nearest
  *     even) to the weight dtype: arc lengths for the piecewise-constant
@@ -86,15 +86,18 @@ typedef struct {
 
 /* Sizes of a plan's operators (for tests, footprints and FLOP counts). */
 typedef struct {
-  int64_t nnz_a12;        /* nonzeros of A12 stacked over columns (rows a*n_radii + l) */
-  int64_t nnz_a34;        /* nonzeros of A34 (rows h*n_radii + l, cols l'*mz + k) */
-  int32_t live_radii;     /* rho cells that any column's circles reach; A34
-                             columns with l' >= live_radii are dropped because
-                             the intermediate image is identically zero there */
+  int64_t nnz_a12;        /* nonzeros of A12 stacked over columns (rows a*n_rho + m) */
+  int64_t nnz_a34;        /* nonzeros of A34 (rows h*n_radii + l, cols m*mz + k) */
+  int32_t live_radii;     /* rho cells (nodes) that any column's circles reach;
+                             A34 columns with m >= live_radii are dropped
+                             because the intermediate image is identically
+                             zero there */
   int32_t n_angles, n_z, n_radii;
   double weight_scale_a12; /* stored weight = exact weight * scale (power of 2) */
   double weight_scale_a34;
   int32_t basis;           /* srt_basis of the plan */
+  int32_t n_rho;           /* size of the stage-2 radial grid (n_radii unless
+                              the plan has a grid of its own) */
 } srt_plan_info;
 
 /*
@@ -141,23 +144,52 @@ srt_status srt_plan_create_columns(const srt_grid *grid, const double *col_xy,
                                    srt_plan **out);
 
 /*
- * srt_plan_create_basis -- as srt_plan_create / srt_plan_create_columns,
- * with the voxel basis chosen (Sec. 3.1).
- *   basis       SRT_BASIS_CONSTANT (what the two calls above build) or
- *               SRT_BASIS_LINEAR
- *   cyl_radius, angles   the cylinder aperture, used when col_xy is NULL
- *   col_xy      host, n_cols (x, y) column positions, or NULL
- *   n_cols      number of columns (angles or positions)
- * Exactly one of angles and col_xy must be non-NULL. Other arguments,
- * outputs and errors as srt_plan_create; an unknown basis is EINVAL.
+ * Full description of a plan, for srt_plan_create_desc. Fields as in
+ * srt_plan_create, plus:
+ *   basis       SRT_BASIS_CONSTANT or SRT_BASIS_LINEAR (Sec. 3.1)
+ *   cyl_radius, angles   a cylinder aperture (used when col_xy is NULL)
+ *   col_xy      host [n_cols][2] column positions anywhere in the plane, or
+ *               NULL; exactly one of angles and col_xy is non-NULL
+ *   rho, n_rho  host [n_rho] radial grid of the stage-2 image, > 0 and
+ *               strictly increasing, or NULL and 0. Sec. 2 evaluates the
+ *               first circular transform at the radii rho that the second
+ *               one integrates over; the paper takes rho = the sphere radii,
+ *               which is what NULL means. A grid of its own makes A12
+ *               n_rho x ms^2 per column and A34 (n_z n_radii) x (n_rho mz):
+ *               coarser grids make stage 1 cheaper and stage 2 smaller at
+ *               some cost in accuracy. Its cells (constant basis) span the
+ *               midpoints between grid values, the outer edges half a spacing
+ *               beyond the ends; its tent nodes (linear basis) are 0, the
+ *               grid values and one spacing past the last.
+ * Data layouts are unchanged ([n_cols][n_z][n_radii]).
  */
-srt_status srt_plan_create_basis(const srt_grid *grid, srt_basis basis, double cyl_radius,
-                                 const double *angles, const double *col_xy, int32_t n_cols,
-                                 const double *z_pos, int32_t n_z,
-                                 const double *radii, int32_t n_radii,
-                                 srt_dtype value_dtype, srt_dtype weight_dtype,
-                                 srt_opmode mode, int32_t device, void *hip_stream,
-                                 srt_plan **out);
+typedef struct {
+  srt_grid grid;
+  srt_basis basis;
+  double cyl_radius;
+  const double *angles;
+  const double *col_xy;
+  int32_t n_cols;
+  const double *z_pos;
+  int32_t n_z;
+  const double *radii;
+  int32_t n_radii;
+  const double *rho;
+  int32_t n_rho;
+  srt_dtype value_dtype;
+  srt_dtype weight_dtype;
+  srt_opmode mode;
+  int32_t device;
+} srt_plan_desc;
+
+/*
+ * srt_plan_create_desc -- build a plan from a full description (any basis,
+ * any column placement, any stage-2 radial grid). desc is read during the
+ * call only. Outputs and errors as srt_plan_create; an unknown basis, both
+ * or neither of angles / col_xy, a rho pointer without a size (or the
+ * reverse) or a rho grid that is not positive and increasing is EINVAL.
+ */
+srt_status srt_plan_create_desc(const srt_plan_desc *desc, void *hip_stream, srt_plan **out);
 
 /*
  * srt_forward -- Alg. 1 for every column and every batch item:
@@ -202,10 +234,10 @@ srt_status srt_plan_get_info(const srt_plan *plan, srt_plan_info *info);
  * srt_plan_export_coo -- copy one stored operator to host memory as COO
  * triplets (row-major order) with weights converted back to exact weights
  * (stored value / scale, as double). For tests.
- *   which     0 = A12 stacked (rows a*n_radii + l, cols j*ms + i),
- *             1 = A34 (rows h*n_radii + l, cols l'*mz + k),
+ *   which     0 = A12 stacked (rows a*n_rho + m, cols j*ms + i),
+ *             1 = A34 (rows h*n_radii + l, cols m*mz + k),
  *             2 = stored transpose of A12 (rows = pixels),
- *             3 = stored transpose of A34 (rows = cells (l', k))
+ *             3 = stored transpose of A34 (rows = cells (m, k))
  *   capacity  length of rows/cols/vals; with capacity 0 the pointers may be
  *             NULL and only *nnz is written
  *   nnz       receives the number of stored entries

@@ -22,7 +22,7 @@ MODES = {"auto": 0, "stored": 1, "onthefly": 2}
 BASES = {"constant": 0, "linear": 1}
 
 # Every entry point declared in include/srt.h.
-SYMBOLS = ("srt_plan_create", "srt_plan_create_columns", "srt_plan_create_basis", "srt_forward", "srt_adjoint", "srt_plan_destroy",
+SYMBOLS = ("srt_plan_create", "srt_plan_create_columns", "srt_plan_create_desc", "srt_forward", "srt_adjoint", "srt_plan_destroy",
            "srt_plan_footprint", "srt_plan_get_info", "srt_plan_export_coo",
            "srt_plan_set_timing", "srt_plan_stage_times", "srt_cgls", "srt_cgls_workspace",
            "srt_last_error")
@@ -39,7 +39,17 @@ class SrtPlanInfo(ctypes.Structure):
                 ("live_radii", ctypes.c_int32), ("n_angles", ctypes.c_int32),
                 ("n_z", ctypes.c_int32), ("n_radii", ctypes.c_int32),
                 ("weight_scale_a12", ctypes.c_double), ("weight_scale_a34", ctypes.c_double),
-                ("basis", ctypes.c_int32)]
+                ("basis", ctypes.c_int32), ("n_rho", ctypes.c_int32)]
+
+
+class SrtPlanDesc(ctypes.Structure):
+    _fields_ = [("grid", SrtGrid), ("basis", ctypes.c_int), ("cyl_radius", ctypes.c_double),
+                ("angles", ctypes.c_void_p), ("col_xy", ctypes.c_void_p),
+                ("n_cols", ctypes.c_int32), ("z_pos", ctypes.c_void_p), ("n_z", ctypes.c_int32),
+                ("radii", ctypes.c_void_p), ("n_radii", ctypes.c_int32),
+                ("rho", ctypes.c_void_p), ("n_rho", ctypes.c_int32),
+                ("value_dtype", ctypes.c_int), ("weight_dtype", ctypes.c_int),
+                ("mode", ctypes.c_int), ("device", ctypes.c_int32)]
 
 
 class SRTError(RuntimeError):
@@ -67,9 +77,7 @@ def lib() -> ctypes.CDLL:
     L.srt_plan_create_columns.argtypes = [ctypes.POINTER(SrtGrid), P, I32, P, I32, P, I32,
                                           ctypes.c_int, ctypes.c_int, ctypes.c_int, I32, P,
                                           ctypes.POINTER(P)]
-    L.srt_plan_create_basis.argtypes = [ctypes.POINTER(SrtGrid), ctypes.c_int, D, P, P, I32, P,
-                                        I32, P, I32, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                        I32, P, ctypes.POINTER(P)]
+    L.srt_plan_create_desc.argtypes = [ctypes.POINTER(SrtPlanDesc), P, ctypes.POINTER(P)]
     L.srt_forward.argtypes = [P, P, P, I32, P, SZ, P]
     L.srt_adjoint.argtypes = [P, P, P, I32, P, SZ, P]
     L.srt_plan_destroy.argtypes = [P]
@@ -145,26 +153,37 @@ def srt_plan_create_columns(ms, mz, x0, z0, dxy, dz, col_xy, z_pos, radii,
     return out.value
 
 
-def srt_plan_create_basis(ms, mz, x0, z0, dxy, dz, basis, z_pos, radii, cyl_radius=0.0,
-                          angles=None, col_xy=None, value_dtype="f32", weight_dtype="f32",
-                          mode="auto", device=0, stream=None) -> int:
-    """Builds a plan on the chosen voxel basis ("constant" or "linear") for a
-    cylinder aperture (cyl_radius, angles) or columns at col_xy (n x 2)."""
+def srt_plan_create_desc(ms, mz, x0, z0, dxy, dz, z_pos, radii, basis="constant",
+                         cyl_radius=0.0, angles=None, col_xy=None, rho=None,
+                         value_dtype="f32", weight_dtype="f32", mode="auto", device=0,
+                         stream=None) -> int:
+    """Builds a plan from a full description: voxel basis ("constant" or
+    "linear"), a cylinder aperture (cyl_radius, angles) or columns at col_xy
+    (n x 2), and optionally a stage-2 radial grid rho of its own."""
     L = lib()
-    grid = SrtGrid(int(ms), int(mz), float(x0), float(z0), float(dxy), float(dz))
-    zp, rad = _f64(z_pos), _f64(radii)
-    ang = None if angles is None else _f64(angles)
-    xy = None if col_xy is None else np.ascontiguousarray(_f64(col_xy).reshape(-1, 2))
-    n = ang.size if ang is not None else (xy.shape[0] if xy is not None else 0)
+    keep = []  # host arrays must outlive the call
+
+    def arr(a, shape=None):
+        if a is None:
+            return None, 0
+        v = _f64(a) if shape is None else np.ascontiguousarray(_f64(a).reshape(shape))
+        keep.append(v)
+        return v.ctypes.data, (v.shape[0] if v.ndim > 1 else v.size)
+
+    ang, n_ang = arr(angles)
+    xy, n_xy = arr(col_xy, (-1, 2))
+    zp, n_z = arr(z_pos)
+    rad, n_rad = arr(radii)
+    rh, n_rh = arr(rho)
+    d = SrtPlanDesc(SrtGrid(int(ms), int(mz), float(x0), float(z0), float(dxy), float(dz)),
+                    BASES[basis], float(cyl_radius), ang, xy, n_ang if ang is not None else n_xy,
+                    zp, n_z, rad, n_rad, rh, n_rh, DTYPES[value_dtype], DTYPES[weight_dtype],
+                    MODES[mode], int(device))
     out = ctypes.c_void_p()
-    st = L.srt_plan_create_basis(ctypes.byref(grid), BASES[basis], float(cyl_radius),
-                                 None if ang is None else ang.ctypes.data,
-                                 None if xy is None else xy.ctypes.data, n,
-                                 zp.ctypes.data, zp.size, rad.ctypes.data, rad.size,
-                                 DTYPES[value_dtype], DTYPES[weight_dtype], MODES[mode],
-                                 int(device), _stream_ptr(stream) if stream is not False else None,
-                                 ctypes.byref(out))
-    _check(st, "srt_plan_create_basis")
+    st = L.srt_plan_create_desc(ctypes.byref(d),
+                                _stream_ptr(stream) if stream is not False else None,
+                                ctypes.byref(out))
+    _check(st, "srt_plan_create_desc")
     return out.value
 
 

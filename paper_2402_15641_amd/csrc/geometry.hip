@@ -1,12 +1,13 @@
 // FP64 arc-length geometry of the two circular Radon transforms.
 //
-// A12 (Sec. 2, circle transform in a z-slice, measure rho dphi): row a*nl + l
+// A12 (Sec. 2, circle transform in a z-slice, measure rho dphi): row a*nr + m
 // holds, for every pixel p = j*ms + i, the length of the circle of radius
-// radii[l] about the centre (cx[a], cy[a]) of column a inside p.
+// rho[m] about the centre (cx[a], cy[a]) of column a inside p.
 // A34 (Sec. 2, half-circle transform, measure l dtheta, theta in [0, pi]):
-// row h*nl + l holds, for every cell (rho cell l', z slice k) with column
-// index l'*mz + k, the length of the half circle of radius radii[l] about
-// (z = zpos[h], rho = 0) inside that cell.
+// row h*nl + l holds, for every cell (rho cell m, z slice k) with column
+// index m*mz + k, the length of the half circle of radius radii[l] about
+// (z = zpos[h], rho = 0) inside that cell. The rho grid is the radii unless
+// the plan was given one of its own.
 //
 // Each row is produced by one thread that walks its circle quadrant by
 // quadrant. Inside a quadrant both coordinates are monotone in the angle, so
@@ -60,8 +61,8 @@ struct UniformEdges {
   }
 };
 
-// Edges of the rho cells: midpoints between consecutive radii, outer edges
-// half a spacing beyond the first and the last radius (n = number of radii).
+// Edges of the rho cells: midpoints between consecutive grid radii, outer
+// edges half a spacing beyond the first and the last (n = grid size).
 struct RhoEdges {
   const double *r;
   int n;
@@ -89,7 +90,7 @@ struct RhoEdges {
   }
 };
 
-// Nodes of the linear basis along rho: 0, the radii, and the last radius
+// Nodes of the linear basis along rho: 0, the grid radii, and the last one
 // plus the last spacing (a single radius r gives 0, r, 2r); n = nl + 1 cells.
 struct RhoNodes {
   const double *r;
@@ -293,15 +294,16 @@ struct LinearEmit {
   }
 };
 
-// A12 row a*nl + l: circle about the column centre over the pixel grid.
+// A12 row a*nr + m: circle of radius rho[m] about the column centre over the
+// pixel grid.
 // Pass 1 (counts != nullptr) stores the piece count; pass 2 fills.
 __global__ void a12_kernel(Geometry g, const int64_t *__restrict__ offs,
                            int64_t *__restrict__ counts, uint64_t *__restrict__ keys,
                            double *__restrict__ vals, int *__restrict__ mismatch) {
   const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (row >= (int64_t)g.na * g.nl) return;
-  const int a = (int)(row / g.nl), l = (int)(row % g.nl);
-  const double cx = g.cx[a], cy = g.cy[a], r = g.radii[l];
+  if (row >= (int64_t)g.na * g.nr) return;
+  const int a = (int)(row / g.nr), m = (int)(row % g.nr);
+  const double cx = g.cx[a], cy = g.cy[a], r = g.rho[m];
   const bool fill = counts == nullptr;
   const uint64_t key = (uint64_t)row * (uint64_t)g.ms * (uint64_t)g.ms;
   uint64_t *kp = fill ? keys + offs[row] : nullptr;
@@ -341,14 +343,14 @@ __global__ void a34_kernel(Geometry g, int live, const int64_t *__restrict__ off
   int64_t k;
   if (g.basis == SRT_BASIS_LINEAR) {
     const UniformEdges ze{g.z0 - 0.5 * g.dz, g.dz, g.mz + 1};  // nodes 0 .. mz+1
-    const RhoNodes re(g.radii, g.nl);
+    const RhoNodes re(g.rho, g.nr);
     LinearEmit<UniformEdges, RhoNodes> e{ze, re, cz, 0.0, r, key, g.mz, g.mz, live,
                                          kp, vp, lim};
     walk_arc(cz, 0.0, r, 2, ze, re, e);
     k = e.k;
   } else {
     const UniformEdges ze{g.z0, g.dz, g.mz};
-    const RhoEdges re{g.radii, g.nl};
+    const RhoEdges re{g.rho, g.nr};
     PieceEmit e{r, key, g.mz, live, kp, vp, lim};
     walk_arc(cz, 0.0, r, 2, ze, re, e);
     k = e.k;
@@ -422,7 +424,7 @@ Status pieces(int64_t nrows, hipStream_t s, Launch launch, Coo *out) {
 }  // namespace
 
 Status a12_pieces(const Geometry &g, hipStream_t s, Coo *out) {
-  const int64_t nrows = (int64_t)g.na * g.nl;
+  const int64_t nrows = (int64_t)g.na * g.nr;
   return pieces(nrows, s,
                 [&](unsigned b, int t, const int64_t *offs, int64_t *counts, uint64_t *keys,
                     double *vals, int *mm) {

@@ -55,26 +55,43 @@ void destroy_contents(srt_plan *p) {
   p->own_ws = nullptr;
 }
 
-// col_xy: host [na][2] column centres (x, y).
+bool strictly_increasing_positive(const double *v, int32_t n) {
+  if (v[0] <= 0) return false;
+  for (int32_t i = 1; i < n; ++i)
+    if (!(v[i] > v[i - 1])) return false;
+  return true;
+}
+
+// col_xy: host [na][2] column centres (x, y). rho: host [nr] radial grid of
+// the stage-2 image, or NULL for the radii themselves.
 Status create(const srt_grid *grid, int32_t basis, const double *col_xy, int32_t na,
               const double *zpos, int32_t nh, const double *radii, int32_t nl,
-              srt_dtype vdt, srt_dtype wdt, srt_opmode mode, int32_t device, hipStream_t s,
-              srt_plan **out) {
+              const double *rho, int32_t nr, srt_dtype vdt, srt_dtype wdt, srt_opmode mode,
+              int32_t device, hipStream_t s, srt_plan **out) {
   if (!out) return fail(SRT_EINVAL, "out is NULL");
   *out = nullptr;
   if (!grid || !col_xy || !zpos || !radii) return fail(SRT_EINVAL, "NULL argument");
   if (basis != SRT_BASIS_CONSTANT && basis != SRT_BASIS_LINEAR)
     return fail(SRT_EINVAL, "unknown basis");
+  const bool own_rho = rho != nullptr;
+  if (!own_rho) {
+    rho = radii;
+    nr = nl;
+  }
   if (grid->ms <= 0 || grid->mz <= 0) return fail(SRT_EINVAL, "grid sizes must be positive");
   if (!(std::isfinite(grid->x0) && std::isfinite(grid->z0) && std::isfinite(grid->dxy) &&
         std::isfinite(grid->dz)) || grid->dxy <= 0 || grid->dz <= 0)
     return fail(SRT_EINVAL, "grid origin and pitch must be finite, pitch > 0");
-  if (na <= 0 || nh <= 0 || nl <= 0) return fail(SRT_EINVAL, "sample counts must be positive");
-  if (!finite_all(col_xy, 2 * (int64_t)na) || !finite_all(zpos, nh) || !finite_all(radii, nl))
+  if (na <= 0 || nh <= 0 || nl <= 0 || nr <= 0)
+    return fail(SRT_EINVAL, "sample counts must be positive");
+  if (!finite_all(col_xy, 2 * (int64_t)na) || !finite_all(zpos, nh) || !finite_all(radii, nl) ||
+      !finite_all(rho, nr))
     return fail(SRT_EINVAL, "sample positions must be finite");
   if (radii[0] <= 0) return fail(SRT_EINVAL, "radii must be > 0");
   for (int32_t i = 1; i < nl; ++i)
     if (!(radii[i] > radii[i - 1])) return fail(SRT_EINVAL, "radii must be strictly increasing");
+  if (own_rho && !strictly_increasing_positive(rho, nr))
+    return fail(SRT_EINVAL, "rho grid must be > 0 and strictly increasing");
   const bool pair_ok = (vdt == SRT_F32 && (wdt == SRT_F32 || wdt == SRT_BF16 || wdt == SRT_F16)) ||
                        (vdt == SRT_F64 && wdt == SRT_F64);
   if (!pair_ok) return fail(SRT_EINVAL, "unsupported (value, weight) dtype pair");
@@ -83,7 +100,8 @@ Status create(const srt_grid *grid, int32_t basis, const double *col_xy, int32_t
   // Index ranges: every dense index below must fit in int32 rows/cols.
   const int64_t npix = (int64_t)grid->ms * grid->ms;
   if (npix > INT32_MAX || (int64_t)na * nl > INT32_MAX || (int64_t)nh * nl > INT32_MAX ||
-      (int64_t)nl * grid->mz > INT32_MAX || npix * grid->mz > ((int64_t)1 << 40))
+      (int64_t)na * nr > INT32_MAX || (int64_t)nr * grid->mz > INT32_MAX ||
+      npix * grid->mz > ((int64_t)1 << 40))
     return fail(SRT_ENOTSUP, "problem too large for 32-bit operator indices");
   int ndev = 0;
   SRT_HIP(hipGetDeviceCount(&ndev));
@@ -101,15 +119,18 @@ Status create(const srt_grid *grid, int32_t basis, const double *col_xy, int32_t
     delete p;
     return st;
   };
-  if (hipMalloc(&p->d_geom, sizeof(double) * (2 * (size_t)na + nh + nl)) != hipSuccess)
+  // device copy: cx[na], cy[na], zpos[nh], radii[nl], rho[nr]
+  const size_t ngeom = 2 * (size_t)na + nh + nl + nr;
+  if (hipMalloc(&p->d_geom, sizeof(double) * ngeom) != hipSuccess)
     return bail(fail(SRT_ENOMEM, "device allocation for geometry failed"));
-  std::vector<double> h(2 * (size_t)na + nh + nl);
-  for (int32_t a = 0; a < na; ++a) {  // cx[], then cy[]
+  std::vector<double> h(ngeom);
+  for (int32_t a = 0; a < na; ++a) {
     h[a] = col_xy[2 * a];
     h[na + a] = col_xy[2 * a + 1];
   }
   std::memcpy(h.data() + 2 * na, zpos, sizeof(double) * nh);
   std::memcpy(h.data() + 2 * na + nh, radii, sizeof(double) * nl);
+  std::memcpy(h.data() + 2 * na + nh + nl, rho, sizeof(double) * nr);
   hipError_t e = hipMemcpyAsync(p->d_geom, h.data(), sizeof(double) * h.size(),
                                 hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -129,6 +150,8 @@ Status create(const srt_grid *grid, int32_t basis, const double *col_xy, int32_t
   g.cy = p->d_geom + na;
   g.zpos = p->d_geom + 2 * na;
   g.radii = p->d_geom + 2 * na + nh;
+  g.rho = p->d_geom + 2 * na + nh + nl;
+  g.nr = nr;
   g.basis = basis;
 
   Coo pieces;
@@ -138,7 +161,7 @@ Status create(const srt_grid *grid, int32_t basis, const double *col_xy, int32_t
     pieces = Coo{};
   };
   Status st = a12_pieces(g, s, &pieces);
-  if (st.ok()) st = compact_a12(&pieces, nl, npix, s, &p->live);
+  if (st.ok()) st = compact_a12(&pieces, nr, npix, s, &p->live);
   if (st.ok())
     st = build_csr_pair(&pieces, (int64_t)na * p->live, npix, wdt, s, &p->a12, &p->a12t);
   free_pieces();
@@ -236,7 +259,7 @@ srt_status srt_plan_create(const srt_grid *grid, double cyl_radius, const double
     Status st = cylinder_columns(cyl_radius, angles, n_angles, &xy);
     if (!st.ok()) return finish(st);
     return finish(create(grid, SRT_BASIS_CONSTANT, xy.data(), n_angles, z_pos, n_z, radii,
-                         n_radii, value_dtype, weight_dtype, mode, device,
+                         n_radii, nullptr, 0, value_dtype, weight_dtype, mode, device,
                          (hipStream_t)hip_stream, out));
   } catch (...) {
     return finish(fail(SRT_ENOMEM, "host exception during plan creation"));
@@ -250,32 +273,32 @@ srt_status srt_plan_create_columns(const srt_grid *grid, const double *col_xy, i
                                    void *hip_stream, srt_plan **out) {
   try {
     return finish(create(grid, SRT_BASIS_CONSTANT, col_xy, n_cols, z_pos, n_z, radii, n_radii,
-                         value_dtype, weight_dtype, mode, device, (hipStream_t)hip_stream,
-                         out));
+                         nullptr, 0, value_dtype, weight_dtype, mode, device,
+                         (hipStream_t)hip_stream, out));
   } catch (...) {
     return finish(fail(SRT_ENOMEM, "host exception during plan creation"));
   }
 }
 
-srt_status srt_plan_create_basis(const srt_grid *grid, srt_basis basis, double cyl_radius,
-                                 const double *angles, const double *col_xy, int32_t n_cols,
-                                 const double *z_pos, int32_t n_z, const double *radii,
-                                 int32_t n_radii, srt_dtype value_dtype,
-                                 srt_dtype weight_dtype, srt_opmode mode, int32_t device,
-                                 void *hip_stream, srt_plan **out) {
+srt_status srt_plan_create_desc(const srt_plan_desc *desc, void *hip_stream, srt_plan **out) {
   try {
     if (out) *out = nullptr;
-    if ((angles == nullptr) == (col_xy == nullptr))
+    if (!desc) return finish(fail(SRT_EINVAL, "NULL argument"));
+    const srt_plan_desc &d = *desc;
+    if ((d.angles == nullptr) == (d.col_xy == nullptr))
       return finish(fail(SRT_EINVAL, "exactly one of angles and col_xy must be given"));
+    if ((d.rho == nullptr) != (d.n_rho == 0))
+      return finish(fail(SRT_EINVAL, "rho and n_rho must both be given or both be absent"));
     std::vector<double> xy;
-    if (angles) {
-      Status st = cylinder_columns(cyl_radius, angles, n_cols, &xy);
+    const double *col_xy = d.col_xy;
+    if (d.angles) {
+      Status st = cylinder_columns(d.cyl_radius, d.angles, d.n_cols, &xy);
       if (!st.ok()) return finish(st);
       col_xy = xy.data();
     }
-    return finish(create(grid, (int32_t)basis, col_xy, n_cols, z_pos, n_z, radii, n_radii,
-                         value_dtype, weight_dtype, mode, device, (hipStream_t)hip_stream,
-                         out));
+    return finish(create(&d.grid, (int32_t)d.basis, col_xy, d.n_cols, d.z_pos, d.n_z, d.radii,
+                         d.n_radii, d.rho, d.n_rho, d.value_dtype, d.weight_dtype, d.mode,
+                         d.device, (hipStream_t)hip_stream, out));
   } catch (...) {
     return finish(fail(SRT_ENOMEM, "host exception during plan creation"));
   }
@@ -299,7 +322,8 @@ srt_status srt_plan_footprint(const srt_plan *plan, int32_t batch, size_t *resid
   if (resident)
     *resident = plan->a12.bytes() + plan->a12t.bytes() + plan->a34.bytes() + plan->a34t.bytes() +
                 plan->t12.bytes() + plan->t12t.bytes() + plan->t34.bytes() + plan->t34t.bytes() +
-                sizeof(double) * ((size_t)plan->geo.na + plan->geo.nh + plan->geo.nl);
+                sizeof(double) * (2 * (size_t)plan->geo.na + plan->geo.nh + plan->geo.nl +
+                                  plan->geo.nr);
   if (workspace) *workspace = workspace_bytes(plan, batch);
   return SRT_OK;
 }
@@ -317,6 +341,7 @@ srt_status srt_plan_get_info(const srt_plan *plan, srt_plan_info *info) {
   info->weight_scale_a12 = plan->a12.scale;
   info->weight_scale_a34 = plan->a34.scale;
   info->basis = plan->geo.basis;
+  info->n_rho = plan->geo.nr;
   return SRT_OK;
 }
 
@@ -344,8 +369,8 @@ srt_status srt_plan_export_coo(const srt_plan *plan, int32_t which, int64_t capa
   if (e != hipSuccess) return finish(hip_fail(e, "export copy"));
   for (int64_t r = 0; r < m->nrows; ++r)
     for (int32_t k = rp[r]; k < rp[r + 1]; ++k) rows[k] = (int32_t)r;
-  // A12 rows are stored as a * live + l; report them as a * n_radii + l.
-  const int64_t L = plan->live, NL = plan->geo.nl;
+  // A12 rows are stored as a * live + m; report them as a * n_rho + m.
+  const int64_t L = plan->live, NL = plan->geo.nr;
   if (which == 0)
     for (int64_t k = 0; k < m->nnz; ++k) rows[k] = (int32_t)((rows[k] / L) * NL + rows[k] % L);
   if (which == 2)

@@ -56,7 +56,9 @@ struct Geometry {
   const double *cx = nullptr;      // device [na] column centre x
   const double *cy = nullptr;      // device [na] column centre y
   const double *zpos = nullptr;    // device [nh]
-  const double *radii = nullptr;   // device [nl]
+  const double *radii = nullptr;   // device [nl] sphere radii (stage-2 half circles)
+  const double *rho = nullptr;     // device [nr] radial grid of the stage-2 image
+  int32_t nr = 0;                  // (stage-1 circle radii); may alias radii
   int32_t basis = SRT_BASIS_CONSTANT;  // voxel basis the weights integrate
 };
 

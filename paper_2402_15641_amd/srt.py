@@ -26,11 +26,14 @@ class SRTPlan:
 
     def __init__(self, ms, mz, x0, z0, dxy, dz, cyl_radius, angles, z_pos, radii,
                  value_dtype: str = "f32", weight_dtype: str | None = None,
-                 device=None, mode: str = "auto", col_xy=None, basis: str = "constant"):
+                 device=None, mode: str = "auto", col_xy=None, basis: str = "constant",
+                 rho=None):
         """col_xy (n x 2), when given, places the sensor columns at arbitrary
         (x, y) positions; cyl_radius and angles are then ignored. basis is
         "constant" (piecewise-constant voxels) or "linear" (volumes hold
-        values at voxel centres, interpolated trilinearly)."""
+        values at voxel centres, interpolated trilinearly). rho, when given,
+        is a radial grid of the stage-2 image of its own (strictly
+        increasing, > 0); by default it is the radii."""
         if weight_dtype is None:
             weight_dtype = value_dtype
         dev = torch.device("cuda", torch.cuda.current_device()) if device is None \
@@ -45,10 +48,10 @@ class SRTPlan:
         self.n_angles, self.n_z, self.n_radii = n_cols, len(z_pos), len(radii)
         self.basis = basis
         with torch.cuda.device(dev):
-            if basis != "constant":
-                self.handle = B.srt_plan_create_basis(
-                    ms, mz, x0, z0, dxy, dz, basis, z_pos, radii, cyl_radius=cyl_radius,
-                    angles=angles if col_xy is None else None, col_xy=col_xy,
+            if basis != "constant" or rho is not None:
+                self.handle = B.srt_plan_create_desc(
+                    ms, mz, x0, z0, dxy, dz, z_pos, radii, basis=basis, cyl_radius=cyl_radius,
+                    angles=angles if col_xy is None else None, col_xy=col_xy, rho=rho,
                     value_dtype=value_dtype, weight_dtype=weight_dtype, mode=mode,
                     device=dev.index or 0)
             elif col_xy is None:
@@ -64,10 +67,12 @@ class SRTPlan:
     @classmethod
     def from_geometry(cls, g, **kw) -> "SRTPlan":
         """From any object with ms, mz, x0, z0, dxy, dz, radius, angles, zpos,
-        radii (and optionally centers: columns at arbitrary (x, y))."""
-        centers = getattr(g, "centers", None)
+        radii (and optionally centers: columns at arbitrary (x, y); rho: a
+        stage-2 radial grid of its own)."""
+        kw.setdefault("col_xy", getattr(g, "centers", None))
+        kw.setdefault("rho", getattr(g, "rho", None))
         return cls(g.ms, g.mz, g.x0, g.z0, g.dxy, g.dz, g.radius, g.angles, g.zpos, g.radii,
-                   col_xy=centers, **kw)
+                   **kw)
 
     @property
     def vol_shape(self):

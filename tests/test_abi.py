@@ -98,29 +98,60 @@ def test_create_columns_rejects_bad_positions():
     assert out.value is None
 
 
-def test_create_basis_rejects_bad_arguments():
+def test_create_desc_rejects_bad_arguments():
     L = B.lib()
-    grid = B.SrtGrid(8, 8, -1.0, -1.0, 0.25, 0.25)
     zp = np.linspace(-1, 1, 3)
     rad = np.linspace(0.1, 3.0, 8)
     ang = np.linspace(0, 6, 4)
     xy = np.array([[1.5, 0.0], [0.1, 0.2]])
 
-    def create(basis, angles, cols, n):
+    def create(basis=1, angles=ang, cols=None, n=4, rho=None, n_rho=0):
+        ptr = lambda a: None if a is None else a.ctypes.data
+        d = B.SrtPlanDesc(B.SrtGrid(8, 8, -1.0, -1.0, 0.25, 0.25), basis, 1.5, ptr(angles),
+                          ptr(cols), n, zp.ctypes.data, 3, rad.ctypes.data, 8, ptr(rho), n_rho,
+                          0, 0, 0, 0)
         out = ctypes.c_void_p(12345)
-        st = L.srt_plan_create_basis(ctypes.byref(grid), basis, 1.5, angles, cols, n,
-                                     zp.ctypes.data, 3, rad.ctypes.data, 8, 0, 0, 0, 0, None,
-                                     ctypes.byref(out))
+        st = L.srt_plan_create_desc(ctypes.byref(d), None, ctypes.byref(out))
         return st, out.value, B.srt_last_error()
 
-    st, out, msg = create(7, ang.ctypes.data, None, 4)
-    assert st == B.SRT_EINVAL and out is None and "basis" in msg
-    st, out, msg = create(1, ang.ctypes.data, xy.ctypes.data, 2)
-    assert st == B.SRT_EINVAL and out is None and "exactly one" in msg
-    st, out, msg = create(1, None, None, 2)
-    assert st == B.SRT_EINVAL and out is None and "exactly one" in msg
-    bad = np.array([0.0, np.nan])
-    st, out, msg = create(1, bad.ctypes.data, None, 2)
-    assert st == B.SRT_EINVAL and "finite" in msg
-    st, out, msg = create(1, None, xy.ctypes.data, 0)
-    assert st == B.SRT_EINVAL and "positive" in msg
+    assert L.srt_plan_create_desc(None, None, ctypes.byref(ctypes.c_void_p())) == B.SRT_EINVAL
+    cases = [
+        (dict(basis=7), "basis"),
+        (dict(cols=xy, n=2), "exactly one"),
+        (dict(angles=None), "exactly one"),
+        (dict(angles=np.array([0.0, np.nan]), n=2), "finite"),
+        (dict(angles=None, cols=xy, n=0), "positive"),
+        (dict(rho=np.array([0.5, 1.0])), "both"),
+        (dict(n_rho=3), "both"),
+        (dict(rho=np.array([0.5, 0.4, 1.0]), n_rho=3), "rho grid"),
+        (dict(rho=np.array([0.0, 0.4, 1.0]), n_rho=3), "rho grid"),
+        (dict(rho=np.array([0.2, np.inf]), n_rho=2), "finite"),
+    ]
+    for over, needle in cases:
+        st, out, msg = create(**over)
+        assert st == B.SRT_EINVAL and out is None and needle in msg, (over, msg)
+
+
+@pytest.mark.parametrize("struct,cname", [("SrtPlanDesc", "srt_plan_desc"),
+                                           ("SrtPlanInfo", "srt_plan_info"),
+                                           ("SrtGrid", "srt_grid")])
+def test_struct_layouts_match_the_header(struct, cname, tmp_path):
+    """The ctypes mirrors have the layout the C compiler gives the header's
+    structs (every field offset and the size)."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no host C compiler")
+    S = getattr(B, struct)
+    fields = [f for f, _ in S._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text("#include <stdio.h>\n#include <stddef.h>\n#include \"srt.h\"\nint main(void){\n"
+                   + f'printf("%zu\\n", sizeof({cname}));\n'
+                   + "".join(f'printf("%zu\\n", offsetof({cname}, {f}));\n' for f in fields)
+                   + "return 0;}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True,
+                                          check=True).stdout.split()]
+    assert got[0] == ctypes.sizeof(S)
+    assert got[1:] == [getattr(S, f).offset for f in fields]

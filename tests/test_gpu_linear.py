@@ -1,4 +1,4 @@
-"""Piecewise-linear voxel basis on the device (srt_plan_create_basis) against
+"""Piecewise-linear voxel basis on the device (srt_plan_create_desc, basis LINEAR) against
 the linear-basis oracle.
 
 Tolerances:
