@@ -17,7 +17,9 @@ Prints one JSON line on stdout. Besides throughput it reports:
   hbm           compulsory bytes of a pair (operators once, input, output)
                 over the pair time, against 8 TB/s
   cpu_baseline  the FP64 oracle timed on the host on a bounded sample of the
-                same workload and scaled to one pair
+                same workload and scaled to one pair: one core, and beside it
+                ("parallel") one process per host core, split by column
+  step_ms       mean, median and minimum of the timed steps (value = 1/mean)
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--weights f32|bf16|f16]
                     [--basis constant|linear] [--n-rho N]
@@ -75,18 +77,16 @@ def measured_traffic(kernel: str, launches_per_pair: int):
     return k["fetch_bytes"] + k["write_bytes"]
 
 
-def cpu_baseline(ap, F64, n_cols=32, h_stride=8):
-    """The oracle (FP64, scipy CSR, one thread) on a bounded sample: Alg. 1
-    and Alg. 2 for n_cols evenly spaced columns, with the stage-2 operator
-    restricted to every h_stride-th sensor height; stage-1 time is scaled by
-    the columns left out, stage-2 time also by the heights left out."""
+def _oracle_sample(ap, F64, cols, heights, barrier=None):
+    """Assembles the sample's operators, then times Alg. 1 and Alg. 2 of the
+    columns `cols` with stage 2 on `heights`: (stage-1 s, stage-2 s, assembly s)."""
     from oracle import geometry as geo, srt as osrt
-    cols = np.linspace(0, ap.n_angles, n_cols, endpoint=False).astype(int)
-    heights = list(range(0, ap.n_z, h_stride))
     t0 = time.perf_counter()
     a34 = geo.assemble_a34(ap, heights=heights)
     a12s = [geo.assemble_a12(ap, ap.angles[a]) for a in cols]
     t_asm = time.perf_counter() - t0
+    if barrier is not None:
+        barrier.wait()  # every process applies at the same time
     t1 = t2 = 0.0
     for A in a12s:
         s = time.perf_counter()
@@ -99,13 +99,65 @@ def cpu_baseline(ap, F64, n_cols=32, h_stride=8):
         s = time.perf_counter()
         osrt.adj_stage1(A, Gp, ap.ms)
         t1 += time.perf_counter() - s
+    return t1, t2, t_asm
+
+
+def _oracle_worker(ap, F64, cols, heights, barrier, queue):
+    queue.put(_oracle_sample(ap, F64, cols, heights, barrier))
+
+
+def cpu_baseline(ap, F64, n_cols=32, h_stride=8, max_procs=16):
+    """The oracle (FP64, scipy CSR) on a bounded sample: Alg. 1 and Alg. 2 for
+    n_cols evenly spaced columns, with the stage-2 operator restricted to
+    every h_stride-th sensor height; stage-1 time is scaled by the columns
+    left out, stage-2 time also by the heights left out. Timed once on one
+    core, then with one process per host core (at most max_procs), the
+    columns split between them and applied concurrently. Runs before the GPU
+    is touched, so the worker processes are plain forks of a CPU-only
+    process."""
+    import multiprocessing as mp
+    import platform
+    cols = np.linspace(0, ap.n_angles, n_cols, endpoint=False).astype(int)
+    heights = list(range(0, ap.n_z, h_stride))
     scale = ap.n_angles / n_cols
+    t1, t2, t_asm = _oracle_sample(ap, F64, cols, heights)
     t_pair = t1 * scale + t2 * scale * h_stride
+    procs = max(1, min(max_procs, len(os.sched_getaffinity(0)), n_cols))
+    ctx = mp.get_context("fork")
+    barrier, queue = ctx.Barrier(procs), ctx.Queue()
+    parts = np.array_split(cols, procs)
+    workers = [ctx.Process(target=_oracle_worker, args=(ap, F64, part, heights, barrier, queue))
+               for part in parts]
+    for w in workers:
+        w.start()
+    res = [queue.get() for _ in workers]
+    for w in workers:
+        w.join()
+    wall = max(a + b * h_stride for a, b, _ in res)  # concurrent: the slowest process
+    t_pair_par = wall * scale
+    model = platform.processor() or platform.machine()
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    threads_env = {k: os.environ[k] for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS",
+                                               "MKL_NUM_THREADS") if k in os.environ}
     return {"value": 1.0 / t_pair, "unit": "pairs/s", "cores": 1, "kind": "oracle",
             "sample": f"{n_cols} of {ap.n_angles} columns, stage 2 on {len(heights)} of "
                       f"{ap.n_z} heights, forward+adjoint, scaled to one full pair "
                       f"(sample apply {t1 + t2:.1f} s, assembly {t_asm:.1f} s not counted)",
-            "seconds_per_pair": t_pair}
+            "seconds_per_pair": t_pair,
+            "parallel": {"value": 1.0 / t_pair_par, "unit": "pairs/s", "cores": procs,
+                         "kind": "oracle",
+                         "sample": f"the same {n_cols} columns split over {procs} processes "
+                                   "(one thread each) applied concurrently; slowest process, "
+                                   "scaled like the one-core figure",
+                         "seconds_per_pair": t_pair_par},
+            "host": {"cpu": model, "affinity_cores": len(os.sched_getaffinity(0)),
+                     "threads_env": threads_env}}
 
 
 def main():
@@ -128,13 +180,8 @@ def main():
               "angle-sharded path is design only", file=sys.stderr)
         sys.exit(2)
 
-    import torch
     from srt_inputs import config, phantoms, with_rho_grid
-    from paper_2402_15641_amd import SRTPlan, binding as B
 
-    if not torch.cuda.is_available():
-        log("bench.py needs a ROCm device")
-        sys.exit(1)
     variant = args.basis != "constant" or args.n_rho > 0
     ap = config(args.workload)
     t0 = time.perf_counter()
@@ -142,8 +189,21 @@ def main():
     if args.n_rho > 0:
         ap = with_rho_grid(ap, args.n_rho)
     log(f"phantom {time.perf_counter() - t0:.1f} s")
+    F_in = F64.astype(np.float32).astype(np.float64)  # the values the GPU receives
+    cpu = None
+    if not args.no_cpu_baseline and not variant:
+        t0 = time.perf_counter()
+        cpu = cpu_baseline(ap, F_in)
+        log(f"cpu baseline {time.perf_counter() - t0:.1f} s: {cpu['value']:.4f} pairs/s on 1 core, "
+            f"{cpu['parallel']['value']:.4f} on {cpu['parallel']['cores']}")
+
+    import torch
+    from paper_2402_15641_amd import SRTPlan, binding as B
+
+    if not torch.cuda.is_available():
+        log("bench.py needs a ROCm device")
+        sys.exit(1)
     vol = torch.from_numpy(F64).float().cuda()
-    F_in = vol.double().cpu().numpy()
 
     t0 = time.perf_counter()
     plan = SRTPlan.from_geometry(ap, value_dtype="f32", weight_dtype=args.weights,
@@ -170,15 +230,16 @@ def main():
     torch.cuda.synchronize()
 
     B.srt_plan_set_timing(plan.handle, True)
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
-    start.record(stream)
-    for _ in range(args.steps):
+    marks[0].record(stream)
+    for i in range(args.steps):
         plan.forward(vol, out=data, workspace=ws)
         plan.adjoint(data, out=back, workspace=ws)
-    stop.record(stream)
+        marks[i + 1].record(stream)
     torch.cuda.synchronize()
-    ms_per_step = start.elapsed_time(stop) / args.steps
+    ms_per_step = marks[0].elapsed_time(marks[-1]) / args.steps
+    steps_ms = [marks[i].elapsed_time(marks[i + 1]) for i in range(args.steps)]
     fwd_ms, n_f = B.srt_plan_stage_times(plan.handle, False)
     adj_ms, n_a = B.srt_plan_stage_times(plan.handle, True)
     B.srt_plan_set_timing(plan.handle, False)
@@ -198,6 +259,13 @@ def main():
     dom_ms, dom_flop = stages[dom]
     achieved = dom_flop / (dom_ms * 1e-3) / 1e12
     traffic = None if variant else measured_traffic(dom, 1)
+    # HBM bytes the counters saw per launch, over each stage kernel's time
+    measured = {}
+    if not variant:
+        for k, (k_ms, _) in stages.items():
+            b = measured_traffic(k, 1)
+            if b is not None:
+                measured[k] = b / (k_ms * 1e-3) / 1e9
 
     wb = {"f32": 4, "bf16": 2, "f16": 2}[args.weights]
     op_bytes = 2 * (nnz12 + nnz34) * (4 + wb)  # operator and its transpose, once each
@@ -229,15 +297,13 @@ def main():
                      "frac": achieved / PEAK_FP32_VALU_TFLOPS, "traffic": traffic,
                      "launch_ms": dom_ms, "flop_per_launch": dom_flop},
         "hbm": {"compulsory_bytes_per_pair": op_bytes + io_bytes, "achieved_gbps": hbm_gbps,
-                "peak_gbps": PEAK_HBM_GBPS, "frac": hbm_gbps / PEAK_HBM_GBPS},
+                "peak_gbps": PEAK_HBM_GBPS, "frac": hbm_gbps / PEAK_HBM_GBPS,
+                "measured_stage_gbps": measured or None},
+        "step_ms": {"mean": ms_per_step, "median": float(np.median(steps_ms)),
+                    "min": float(np.min(steps_ms))},
         "stage_ms": {"forward": fwd_ms, "adjoint": adj_ms},
+        "cpu_baseline": cpu,
     }
-    if not args.no_cpu_baseline and not variant:
-        t0 = time.perf_counter()
-        result["cpu_baseline"] = cpu_baseline(ap, F_in)
-        log(f"cpu baseline {time.perf_counter() - t0:.1f} s")
-    else:
-        result["cpu_baseline"] = None
     plan.close()
     print(json.dumps(result), flush=True)
 
