@@ -101,9 +101,12 @@ constexpr int kE64 = 960;  // padded entries staged in LDS per chunk (FP64 value
 constexpr int kRB = 128;
 constexpr int kC = 64;
 constexpr int kE32 = 940;  // two workgroups' double buffers fit one CU's LDS
-constexpr int kE64 = 470;
+constexpr int kE64 = 468;
 #endif
 constexpr int kQ = 4;      // rows per quad: a lane group runs a quad in lockstep
+// whole quads per chunk, so that every step's four entries start on a
+// 16-byte boundary in LDS (the clamped read past a segment's end included)
+static_assert(kE32 % kQ == 0 && kE64 % kQ == 0, "entries per chunk come in whole quads");
 constexpr int kNQ = kRB / kQ;  // quads per block
 constexpr int kNW = SRT_WG_WAVES;  // wavefronts per workgroup
 

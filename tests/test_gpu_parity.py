@@ -123,6 +123,51 @@ def test_ragged_shapes(ms, mz, R, na, nh, nl, batch, value):
     assert rel_l2(_np(plan.adjoint(dtt)), oracle_adjoint(ap, a12s, a34, _np(dtt))) <= tol
 
 
+MINIMAL = [
+    # ms, mz, R, na, nh, nl: single-element axes
+    (1, 1, 0.7, 1, 1, 1),
+    (2, 1, 1.5, 1, 1, 1),
+    (5, 1, 1.2, 3, 1, 2),
+    (1, 4, 0.3, 2, 3, 1),
+    (3, 2, 0.0, 1, 2, 3),
+]
+
+
+@pytest.mark.parametrize("ms,mz,R,na,nh,nl", MINIMAL)
+@pytest.mark.parametrize("basis", ["constant", "linear"])
+def test_minimal_shapes(ms, mz, R, na, nh, nl, basis):
+    """One pixel, one slice, one radius, one height or one column, on both
+    bases (FP64, batch 2) against the oracle."""
+    from oracle import linear as lin
+    from paper_2402_15641_amd import SRTPlan
+    ap = cylinder_aperture("min", ms, 1.0, R, na, nh, nl, l_max=2.5, mz=mz)
+    a12s, a34 = (geo if basis == "constant" else lin).assemble_all(ap)
+    rng = np.random.default_rng(ms * 100 + mz * 10 + nl)
+    vols = rng.uniform(-1, 1, (2,) + ap.vol_shape)
+    data = rng.standard_normal((2,) + ap.data_shape)
+    plan = SRTPlan.from_geometry(ap, value_dtype="f64", basis=basis)
+    assert rel_l2(_np(plan.forward(_t(vols, torch.float64))),
+                  oracle_forward(ap, a12s, a34, vols)) <= 1e-12
+    assert rel_l2(_np(plan.adjoint(_t(data, torch.float64))),
+                  oracle_adjoint(ap, a12s, a34, data)) <= 1e-12
+
+
+def test_empty_batch():
+    """batch 0 is an argument error at the C ABI; the torch wrapper returns an
+    empty result without calling it."""
+    import ctypes
+    from paper_2402_15641_amd import binding as B
+    ap, _, _ = operators("grid32")
+    plan = _plan(ap, "f32")
+    vol = torch.zeros((0,) + ap.vol_shape, device="cuda")
+    assert plan.forward(vol).shape == (0,) + ap.data_shape
+    assert plan.adjoint(torch.zeros((0,) + ap.data_shape, device="cuda")).shape == vol.shape
+    out = torch.empty(ap.data_shape, device="cuda")
+    one = torch.zeros(ap.vol_shape, device="cuda")
+    st = B.lib().srt_forward(plan.handle, one.data_ptr(), out.data_ptr(), 0, None, 0, None)
+    assert st == B.SRT_EINVAL and "batch" in B.srt_last_error()
+
+
 def test_no_sphere_reaches_the_grid():
     """Sensors far away with short radii: both transforms are exactly zero."""
     ap = cylinder_aperture("far", 8, 1.0, 50.0, 4, 3, 5, l_max=2.0)
