@@ -18,6 +18,7 @@
 //   data [b][a][h][l]     caller layout
 // L = live rho cells (circles of larger radius miss the grid).
 #include <algorithm>
+#include <type_traits>
 
 #include "srt_internal.h"
 
@@ -113,21 +114,30 @@ template <> struct Quad4<float, float> {
     w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
   }
 };
-template <> struct Quad4<float, uint16_t> {  // bfloat16: the upper half of an f32
-  static __device__ __forceinline__ void load(const uint32_t *raw, int e, float w[4]) {
-    const uint2 v = *reinterpret_cast<const uint2 *>(raw + e / 2);
-    w[0] = __uint_as_float(v.x << 16); w[1] = __uint_as_float(v.x & 0xffff0000u);
-    w[2] = __uint_as_float(v.y << 16); w[3] = __uint_as_float(v.y & 0xffff0000u);
-  }
-};
-template <> struct Quad4<float, _Float16> {
-  static __device__ __forceinline__ void load(const uint32_t *raw, int e, float w[4]) {
-    const _Float16 *h = reinterpret_cast<const _Float16 *>(raw) + e;
-    typedef _Float16 h4 __attribute__((ext_vector_type(4)));
-    const h4 v = *reinterpret_cast<const h4 *>(h);
-    w[0] = (float)v.x; w[1] = (float)v.y; w[2] = (float)v.z; w[3] = (float)v.w;
-  }
-};
+// A packed 16-bit unit (one quad step): weights in words x, y (two per
+// word, low half first), local columns in words z, w.
+template <typename WT> __device__ __forceinline__ float half_weight(uint32_t bits16);
+template <> __device__ __forceinline__ float half_weight<uint16_t>(uint32_t b) {  // bfloat16
+  return __uint_as_float(b << 16);
+}
+template <> __device__ __forceinline__ float half_weight<_Float16>(uint32_t b) {
+  // converted once per step; left to itself the compiler folds the
+  // conversion into every FMA (v_fma_mix_f32), which measured slower
+  float f = (float)__builtin_bit_cast(_Float16, (uint16_t)b);
+  asm volatile("" : "+v"(f));
+  return f;
+}
+template <typename WT>
+__device__ __forceinline__ void unpack_unit(const uint4 u, int c[4], float w[4]) {
+  w[0] = half_weight<WT>(u.x & 0xffffu);
+  w[1] = half_weight<WT>(u.x >> 16);
+  w[2] = half_weight<WT>(u.y & 0xffffu);
+  w[3] = half_weight<WT>(u.y >> 16);
+  c[0] = (int)(u.z & 0xffffu);
+  c[1] = (int)(u.z >> 16);
+  c[2] = (int)(u.w & 0xffffu);
+  c[3] = (int)(u.w >> 16);
+}
 template <> struct Quad4<double, double> {
   static __device__ __forceinline__ void load(const uint32_t *raw, int e, double w[4]) {
     const double2 a = *reinterpret_cast<const double2 *>(raw + 2 * e);
@@ -138,11 +148,15 @@ template <> struct Quad4<double, double> {
 
 // One chunk's worth of LDS: staged dense rows (row kC stays zero and is what
 // padding entries point at) and the entries' local columns and weights (as
-// stored). The quads' entry offsets and first entries travel in registers.
+// stored; 16-bit weights come packed with their columns, one 16-byte unit per
+// quad step, and need no column array). The quads' entry offsets and first
+// entries travel in registers.
 template <typename T, typename WT> struct ChunkLds {
   using V16 = typename Vec16<T>::type;
+  static constexpr bool PACKED = sizeof(WT) == 2;
   static constexpr int E = TileShape<T>::E;
-  static constexpr int WWORDS = E * (int)sizeof(WT) / 4;
+  static constexpr int CWORDS = PACKED ? 1 : E;
+  static constexpr int WWORDS = PACKED ? E : E * (int)sizeof(WT) / 4;
   V16 *dense;
   int32_t *col;
   uint32_t *w;
@@ -183,14 +197,14 @@ __device__ __forceinline__ void tiled_body(const int32_t *__restrict__ blk_rows,
                                            const WT *__restrict__ ent_w, const T *__restrict__ X,
                                            T *__restrict__ Y, int nblk, int D, T scale,
                                            int remap, uint32_t xbytes) {
-  constexpr bool VEC = MODE != 0, BUF = MODE == 1;
+  constexpr bool VEC = MODE != 0, BUF = MODE == 1, PACKED = ChunkLds<T, WT>::PACKED;
   using S = TileShape<T>;
   using V16 = typename Vec16<T>::type;
   using L = ChunkLds<T, WT>;
   constexpr int VS = S::VS, NV = S::NV, DW = S::DW, PIECES = S::PIECES;
   constexpr int LPG = S::LPG, GROUPS = S::GROUPS, E = S::E, PPW = S::PAIRS_PER_WAVE;
   __shared__ V16 dense0[(kC + 1) * PIECES], dense1[(kC + 1) * PIECES];
-  __shared__ int32_t col0[E], col1[E];
+  __shared__ int32_t col0[L::CWORDS], col1[L::CWORDS];
   __shared__ uint32_t w0[L::WWORDS], w1[L::WWORDS];
   const L buf0{dense0, col0, w0}, buf1{dense1, col1, w1};
 
@@ -260,24 +274,30 @@ __device__ __forceinline__ void tiled_body(const int32_t *__restrict__ blk_rows,
                    b.dense + u * PIECES + (i & 1) * (64 / WPV));
       }
     }
-    const int nw = ne * (int)sizeof(WT) / 4;
+    // weight words (packed: whole units, four bytes per entry)
+    const int nw = PACKED ? ne : ne * (int)sizeof(WT) / 4;
+    const uint32_t *wsrc = PACKED ? reinterpret_cast<const uint32_t *>(ent_w) + ce0
+                                  : reinterpret_cast<const uint32_t *>(ent_w + ce0);
     if constexpr (BUF) {
-      const auto rc = buf_rsrc(ent_col + ce0, (uint32_t)ne * 4u);
-      for (int j = wave; j * 64 < ne; j += kNW) {
-        const int i = j * 64 + lane;
-        if (i < ne) buf_dma4(rc, (uint32_t)i * 4u, b.col + j * 64);
+      if constexpr (!PACKED) {
+        const auto rc = buf_rsrc(ent_col + ce0, (uint32_t)ne * 4u);
+        for (int j = wave; j * 64 < ne; j += kNW) {
+          const int i = j * 64 + lane;
+          if (i < ne) buf_dma4(rc, (uint32_t)i * 4u, b.col + j * 64);
+        }
       }
-      const auto rw = buf_rsrc(ent_w + ce0, (uint32_t)nw * 4u);
+      const auto rw = buf_rsrc(wsrc, (uint32_t)nw * 4u);
       for (int j = wave; j * 64 < nw; j += kNW) {
         const int i = j * 64 + lane;
         if (i < nw) buf_dma4(rw, (uint32_t)i * 4u, b.w + j * 64);
       }
     } else {
-      for (int j = wave; j * 64 < ne; j += kNW) {
-        const int i = j * 64 + lane;
-        if (i < ne) lds_dma4(ent_col + ce0 + i, b.col + j * 64);
+      if constexpr (!PACKED) {
+        for (int j = wave; j * 64 < ne; j += kNW) {
+          const int i = j * 64 + lane;
+          if (i < ne) lds_dma4(ent_col + ce0 + i, b.col + j * 64);
+        }
       }
-      const uint32_t *wsrc = reinterpret_cast<const uint32_t *>(ent_w + ce0);
       for (int j = wave; j * 64 < nw; j += kNW) {
         const int i = j * 64 + lane;
         if (i < nw) lds_dma4(wsrc + i, b.w + j * 64);
@@ -287,11 +307,16 @@ __device__ __forceinline__ void tiled_body(const int32_t *__restrict__ blk_rows,
   // This lane group's quad: its entry range in chunk c and its first step's
   // entries (columns and weights), read from memory, not from LDS.
   const int q = wave * GROUPS + grp;
-  struct Head {
+  struct HeadU {  // unpacked layouts: the first step's columns and weights
     int e0, e1;
     int4 cn;
     T wn[kQ];
   };
+  struct HeadP {  // packed layout: the first step's unit
+    int e0, e1;
+    uint4 un;
+  };
+  using Head = std::conditional_t<PACKED, HeadP, HeadU>;
   auto load_range = [&](int c, Head &h) {
     const int32_t *qs = qseg + (size_t)c * (kNQ + 1) + q;
     h.e0 = qs[0];
@@ -300,25 +325,41 @@ __device__ __forceinline__ void tiled_body(const int32_t *__restrict__ blk_rows,
   auto load_first = [&](int c, Head &h) {
     // an empty segment reads the chunk's first entries instead (in range)
     const int e = chunk_ent[c] + (h.e0 < h.e1 ? h.e0 : 0);
-    h.cn = *reinterpret_cast<const int4 *>(ent_col + e);
-    Quad4<T, WT>::load(reinterpret_cast<const uint32_t *>(ent_w), e, h.wn);
+    if constexpr (PACKED) {
+      h.un = *reinterpret_cast<const uint4 *>(reinterpret_cast<const uint32_t *>(ent_w) + e);
+    } else {
+      h.cn = *reinterpret_cast<const int4 *>(ent_col + e);
+      Quad4<T, WT>::load(reinterpret_cast<const uint32_t *>(ent_w), e, h.wn);
+    }
   };
   // This lane group's quad over one staged chunk.
   auto consume = [&](const L &b, const Head &h) {
     const int e0 = h.e0, e1 = h.e1;
-    int4 cn = h.cn;
+    int4 cn;
+    uint4 un;
     T wn[kQ];
-#pragma unroll
-    for (int j = 0; j < kQ; ++j) wn[j] = h.wn[j];
     // Keep the loop's own entry reads where they are written (a step ahead):
     // without this the compiler merges them with these first reads into one
     // read at the top of the loop, which stalls every step on it.
-    asm volatile("" : "+v"(cn.x), "+v"(cn.y), "+v"(cn.z), "+v"(cn.w));
-    for (int e = e0; e < e1; e += kQ) {
-      const int cj[kQ] = {cn.x, cn.y, cn.z, cn.w};
-      T ww[kQ];
+    if constexpr (PACKED) {
+      un = h.un;
+      asm volatile("" : "+v"(un.x), "+v"(un.y), "+v"(un.z), "+v"(un.w));
+    } else {
+      cn = h.cn;
 #pragma unroll
-      for (int j = 0; j < kQ; ++j) ww[j] = wn[j];
+      for (int j = 0; j < kQ; ++j) wn[j] = h.wn[j];
+      asm volatile("" : "+v"(cn.x), "+v"(cn.y), "+v"(cn.z), "+v"(cn.w));
+    }
+    for (int e = e0; e < e1; e += kQ) {
+      int cj[kQ];
+      T ww[kQ];
+      if constexpr (PACKED) {
+        unpack_unit<WT>(un, cj, ww);
+      } else {
+        cj[0] = cn.x; cj[1] = cn.y; cj[2] = cn.z; cj[3] = cn.w;
+#pragma unroll
+        for (int j = 0; j < kQ; ++j) ww[j] = wn[j];
+      }
       V16 x[kQ][NV];
 #pragma unroll
       for (int j = 0; j < kQ; ++j)
@@ -327,8 +368,12 @@ __device__ __forceinline__ void tiled_body(const int32_t *__restrict__ blk_rows,
       // next step's entries, read while this step's rows are in flight
       // (clamped: the read after the last step is unused)
       const int en = min(e + kQ, E - kQ);
-      cn = *reinterpret_cast<const int4 *>(b.col + en);
-      Quad4<T, WT>::load(b.w, en, wn);
+      if constexpr (PACKED) {
+        un = *reinterpret_cast<const uint4 *>(b.w + en);
+      } else {
+        cn = *reinterpret_cast<const int4 *>(b.col + en);
+        Quad4<T, WT>::load(b.w, en, wn);
+      }
 #pragma unroll
       for (int j = 0; j < kQ; ++j)
 #pragma unroll

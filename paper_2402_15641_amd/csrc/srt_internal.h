@@ -132,6 +132,10 @@ struct Tiled {
   int32_t *qseg = nullptr;         // [nchunk * (kNQ + 1)] quad offsets within the chunk
   int32_t *ent_col = nullptr;      // [nnz] local column (kC = the all-zero padding column)
   void *ent_w = nullptr;           // [nnz] weights in wdtype (0 for padding)
+  // With 16-bit weights the entries are packed instead: ent_col is null and
+  // ent_w holds one 16-byte unit per quad step (entries 4u .. 4u+3): their
+  // four weights (as stored), then their four local columns (16-bit each).
+  bool packed = false;
   srt_dtype wdtype = SRT_F32;
   double scale = 1.0;
   size_t bytes() const;

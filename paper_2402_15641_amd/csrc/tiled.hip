@@ -28,7 +28,8 @@
 //   chunk_ncols[c]                columns in chunk c
 //   chunk_ent[c] .. [c+1]         padded entries of chunk c
 //   qseg[c*(kNQ+1) + q]           first entry of quad q, relative to chunk_ent[c]
-//   ent_col[e], ent_w[e]          local column and weight of entry e
+//   ent_col[e], ent_w[e]          local column and weight of entry e (16-bit
+//                                 weights: packed units, see Tiled::packed)
 #include <hipcub/hipcub.hpp>
 
 #include "srt_internal.h"
@@ -238,6 +239,12 @@ __global__ void k_pad_fill(int64_t n, int32_t *__restrict__ ent_col) {
   if (i < n) ent_col[i] = kC;
 }
 
+// Packed 16-bit entries: padding units have zero weights and columns kC.
+__global__ void k_pad_fill_packed(int64_t nwords, uint32_t *__restrict__ pack) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nwords) pack[i] = (i & 2) ? ((uint32_t)kC | ((uint32_t)kC << 16)) : 0u;
+}
+
 // Entry i (in (chunk, slot) order) goes to row j = slot % kQ of its quad at
 // padded position kQ * k + j, k = its rank within the row segment.
 template <typename W>
@@ -256,6 +263,26 @@ __global__ void k_scatter(const uint64_t *__restrict__ key2s, const int32_t *__r
   const int32_t src = perm2[i];  // position in (block, column) order
   ent_col[dst] = local[src];
   ent_w[dst] = vals[idx_sorted[src]];
+}
+
+// As k_scatter, into the packed 16-bit layout: entry dst is lane j = dst % 4
+// of unit dst / 4 (halfwords 0-3 weights, 4-7 local columns).
+__global__ void k_scatter_packed(const uint64_t *__restrict__ key2s, const int32_t *__restrict__ perm2,
+                                 int64_t nnz, const int64_t *__restrict__ rawstart,
+                                 const int64_t *__restrict__ qstart, const int32_t *__restrict__ local,
+                                 const int32_t *__restrict__ idx_sorted,
+                                 const uint16_t *__restrict__ vals, uint16_t *__restrict__ pack) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nnz) return;
+  const int64_t sid = (int64_t)key2s[i];
+  const int64_t c = sid / kRB;
+  const int slot = (int)(sid % kRB);
+  const int64_t k = i - rawstart[sid];
+  const int64_t dst = qstart[c * kNQ + slot / kQ] + kQ * k + slot % kQ;
+  const int32_t src = perm2[i];
+  const int64_t u = dst >> 2, j = dst & 3;
+  pack[u * 8 + j] = vals[idx_sorted[src]];
+  pack[u * 8 + 4 + j] = (uint16_t)local[src];
 }
 
 int bits_for(uint64_t v) {
@@ -278,8 +305,8 @@ Status scan_to_i64(const In *in, int64_t *out, int64_t n, hipStream_t s, F oom) 
 
 size_t Tiled::bytes() const {
   return sizeof(int32_t) * ((size_t)nblk * kRB + nblk + 1 + (size_t)nchunk * (kC + 1) + nchunk + 1 +
-                            (size_t)nchunk * (kNQ + 1) + (size_t)nnz) +
-         dtype_size(wdtype) * (size_t)nnz;
+                            (size_t)nchunk * (kNQ + 1)) +
+         (packed ? 4 : sizeof(int32_t) + dtype_size(wdtype)) * (size_t)nnz;
 }
 
 void Tiled::release() {
@@ -409,12 +436,22 @@ Status build_tiled(const Csr &m, const RowGrid &g, int max_ent, hipStream_t s, T
   if (npad >= INT32_MAX) return fail(SRT_ENOTSUP, "too many padded operator entries");
   T.nnz = npad;
   const size_t wsz = dtype_size(m.wdtype);
-  if (hipMalloc(&T.ent_col, sizeof(int32_t) * (npad > 0 ? npad : 1)) != hipSuccess ||
-      hipMalloc(&T.ent_w, wsz * (npad > 0 ? npad : 1)) != hipSuccess)
-    return oom();
-  if (npad > 0) {
-    hipLaunchKernelGGL(k_pad_fill, dim3(nblocks(npad, t)), dim3(t), 0, s, npad, T.ent_col);
-    SRT_HIP(hipMemsetAsync(T.ent_w, 0, wsz * npad, s));
+  // npad is a multiple of kQ (every quad segment is), so packed entries form
+  // whole 16-byte units
+  T.packed = wsz == 2;
+  if (T.packed) {
+    if (hipMalloc(&T.ent_w, 4 * (size_t)(npad > 0 ? npad : 4)) != hipSuccess) return oom();
+    if (npad > 0)
+      hipLaunchKernelGGL(k_pad_fill_packed, dim3(nblocks(npad, t)), dim3(t), 0, s, npad,
+                         (uint32_t *)T.ent_w);
+  } else {
+    if (hipMalloc(&T.ent_col, sizeof(int32_t) * (npad > 0 ? npad : 1)) != hipSuccess ||
+        hipMalloc(&T.ent_w, wsz * (npad > 0 ? npad : 1)) != hipSuccess)
+      return oom();
+    if (npad > 0) {
+      hipLaunchKernelGGL(k_pad_fill, dim3(nblocks(npad, t)), dim3(t), 0, s, npad, T.ent_col);
+      SRT_HIP(hipMemsetAsync(T.ent_w, 0, wsz * npad, s));
+    }
   }
   hipLaunchKernelGGL(k_chunk_meta2, dim3(nblocks(nchunk * (kNQ + 1) + 1, t)), dim3(t), 0, s,
                      qstart.as<int64_t>(), nchunk, T.chunk_ent, T.qseg);
@@ -433,10 +470,10 @@ Status build_tiled(const Csr &m, const RowGrid &g, int max_ent, hipStream_t s, T
                            (const uint32_t *)m.vals, T.ent_col, (uint32_t *)T.ent_w);
         break;
       default:
-        hipLaunchKernelGGL(k_scatter<uint16_t>, dim3(nblocks(nnz, t)), dim3(t), 0, s,
+        hipLaunchKernelGGL(k_scatter_packed, dim3(nblocks(nnz, t)), dim3(t), 0, s,
                            key2s.as<uint64_t>(), perm2.as<int32_t>(), nnz, rawstart.as<int64_t>(),
                            qstart.as<int64_t>(), local.as<int32_t>(), idx_sorted.as<int32_t>(),
-                           (const uint16_t *)m.vals, T.ent_col, (uint16_t *)T.ent_w);
+                           (const uint16_t *)m.vals, (uint16_t *)T.ent_w);
     }
   }
   SRT_HIP(hipGetLastError());
