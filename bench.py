@@ -20,6 +20,9 @@ Prints one JSON line on stdout. Besides throughput it reports:
                 same workload and scaled to one pair: one core, and beside it
                 ("parallel") one process per host core, split by column
   step_ms       mean, median and minimum of the timed steps (value = 1/mean)
+  bf16_weights  the same pair with BF16-stored weights (FP32 values and
+                accumulation): rate and relative L2 distance from the FP32-weight
+                results (default run only)
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--weights f32|bf16|f16]
                     [--basis constant|linear] [--n-rho N]
@@ -304,6 +307,28 @@ def main():
         "stage_ms": {"forward": fwd_ms, "adjoint": adj_ms},
         "cpu_baseline": cpu,
     }
+    if not variant and args.weights == "f32":
+        # the same pair with BF16-stored weights (FP32 values and accumulation)
+        p16 = SRTPlan.from_geometry(ap, value_dtype="f32", weight_dtype="bf16")
+        d16 = torch.empty_like(data)
+        b16 = torch.empty_like(back)
+        for _ in range(args.warmup):
+            p16.forward(vol, out=d16, workspace=ws)
+            p16.adjoint(d16, out=b16, workspace=ws)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            p16.forward(vol, out=d16, workspace=ws)
+            p16.adjoint(d16, out=b16, workspace=ws)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms16 = e0.elapsed_time(e1) / args.steps
+        result["bf16_weights"] = {
+            "value": 1000.0 / ms16, "unit": "pairs/s", "ms_per_step": ms16,
+            "rel_l2_forward_vs_f32_weights": float((d16 - data).norm() / data.norm()),
+            "rel_l2_adjoint_vs_f32_weights": float((b16 - back).norm() / back.norm())}
+        p16.close()
     plan.close()
     print(json.dumps(result), flush=True)
 

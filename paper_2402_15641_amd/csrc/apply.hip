@@ -502,14 +502,69 @@ __global__ __launch_bounds__(256) void transpose_kernel(const T *__restrict__ in
   }
 }
 
+// The same transpose with 16-byte accesses: loads along c, stores along r
+// (each a run of 16 lanes covering one 256-byte row segment of the tile).
+// Needs R, C, every stride and both base addresses to be whole 16-byte
+// vectors. The tile's odd row pitch keeps both phases free of LDS bank
+// conflicts (the lanes of one access hit 64 distinct banks).
+template <typename T>
+__global__ __launch_bounds__(256) void transpose_vec_kernel(const T *__restrict__ in,
+                                                            T *__restrict__ out, TDesc t) {
+  using V16 = typename Vec16<T>::type;
+  constexpr int VS = 16 / sizeof(T);  // values per vector
+  constexpr int LPR = 64 / VS;        // lanes per 64-value row segment
+  constexpr int RPP = 256 / LPR;      // rows per pass of the workgroup
+  __shared__ T tile[64][65];
+  const int ctiles = (t.C + 63) / 64;
+  const int bx = blockIdx.x;
+  const int ct = bx % ctiles;
+  const int b = bx / ctiles;
+  const int b1 = b / t.n2, b2 = b % t.n2;
+  const int r0 = blockIdx.y * 64, c0 = ct * 64;
+  const int tid = threadIdx.x, seg = (tid % LPR) * VS, sub = tid / LPR;
+  const T *ib = in + b1 * t.ib1 + b2 * t.ib2;
+  T *ob = out + b1 * t.ob1 + b2 * t.ob2;
+#pragma unroll
+  for (int i = 0; i < 64 / RPP; ++i) {
+    const int rr = sub + RPP * i, r = r0 + rr, c = c0 + seg;
+    if (r < t.R && c < t.C) {  // C is a whole number of vectors: c < C covers c + VS - 1
+      const V16 v = *reinterpret_cast<const V16 *>(ib + (int64_t)r * t.irs + c);
+      const T *vs = reinterpret_cast<const T *>(&v);
+#pragma unroll
+      for (int k = 0; k < VS; ++k) tile[rr][seg + k] = vs[k];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 64 / RPP; ++i) {
+    const int cc = sub + RPP * i, c = c0 + cc, r = r0 + seg;
+    if (c < t.C && r < t.R) {
+      V16 v;
+      T *vs = reinterpret_cast<T *>(&v);
+#pragma unroll
+      for (int k = 0; k < VS; ++k) vs[k] = tile[seg + k][cc];
+      *reinterpret_cast<V16 *>(ob + (int64_t)c * t.ocs + r) = v;
+    }
+  }
+}
+
 template <typename T>
 Status transpose(const T *in, T *out, const TDesc &t, hipStream_t s) {
   if (t.R <= 0 || t.C <= 0 || t.n1 <= 0 || t.n2 <= 0) return Status{};
   const int64_t gx = (int64_t)t.n1 * t.n2 * ((t.C + 63) / 64);
   const int64_t gy = (t.R + 63) / 64;
   if (gx > INT32_MAX || gy > 65535) return fail(SRT_ENOTSUP, "transpose grid too large");
-  hipLaunchKernelGGL(transpose_kernel<T>, dim3((unsigned)gx, (unsigned)gy), dim3(256), 0, s, in,
-                     out, t);
+  constexpr int64_t VS = 16 / sizeof(T);
+  const bool vec = t.R % VS == 0 && t.C % VS == 0 && t.irs % VS == 0 && t.ib1 % VS == 0 &&
+                   t.ib2 % VS == 0 && t.ocs % VS == 0 && t.ob1 % VS == 0 && t.ob2 % VS == 0 &&
+                   reinterpret_cast<uintptr_t>(in) % 16 == 0 &&
+                   reinterpret_cast<uintptr_t>(out) % 16 == 0;
+  if (vec)
+    hipLaunchKernelGGL(transpose_vec_kernel<T>, dim3((unsigned)gx, (unsigned)gy), dim3(256), 0, s,
+                       in, out, t);
+  else
+    hipLaunchKernelGGL(transpose_kernel<T>, dim3((unsigned)gx, (unsigned)gy), dim3(256), 0, s, in,
+                       out, t);
   SRT_HIP(hipGetLastError());
   return Status{};
 }

@@ -272,6 +272,25 @@ def test_pact256_sampled_forward_and_sparse_adjoint():
     assert rel_l2(Fp, ref) <= 1e-5
 
 
+@pytest.mark.parametrize("weight", ["bf16", "f16"])
+def test_pact256_sampled_forward_16bit_weights(weight):
+    """At 256^3 with 16-bit weights (the packed entry layout, in the launch
+    configuration the benchmark times): sampled forward outputs against the
+    FP64 oracle within the 16-bit-weight bar, 5e-3 relative L2."""
+    ap = config("pact256")
+    Ft = _t(phantoms.phantom(ap), torch.float32)
+    Fin = _np(Ft)
+    plan = _plan(ap, "f32", weight)
+    Y = _np(plan.forward(Ft))
+    angles, heights = [3, 260], [17, 200]
+    a34 = geo.assemble_a34(ap, heights=heights)
+    for a in angles:
+        G = osrt.stage1(geo.assemble_a12(ap, ap.angles[a]), Fin).reshape(-1)
+        for h in heights:
+            rows = a34[h * ap.n_radii:(h + 1) * ap.n_radii]
+            assert rel_l2(Y[a, h], rows @ G) <= 5e-3, (a, h)
+
+
 def test_pact256_batch_over_4gib_matches_single():
     """A batch of 11 at 256^3 makes every stage's dense operand span 4 GiB or
     more except stage 1's forward input, so those stages stage their rows by
