@@ -1,5 +1,6 @@
-"""A stage-2 radial grid of its own (srt_plan_create_desc with rho) against
-the oracle, on both voxel bases.
+"""A stage-2 radial grid of its own (srt_plan_create_desc with rho), and
+non-uniform sensor radii with the tied grid, against the oracle, on both
+voxel bases.
 
 Tolerances as for the tied grid: operator entries (FP64) 1e-12 * pitch per
 entry; forward / adjoint relative L2 1e-12 (FP64), 1e-5 (FP32). The stage
@@ -46,12 +47,20 @@ def _graded(ap, n):
     return dataclasses.replace(ap, name=ap.name + "_graded", rho=ap.radii[-1] * u ** 1.5)
 
 
+def _graded_radii(ap):
+    u = np.arange(1, ap.n_radii + 1) / ap.n_radii
+    return dataclasses.replace(ap, name=ap.name + "_gr", radii=ap.radii[-1] * u ** 1.7)
+
+
 APERTURES = {
     # coarser than the radii (45 radii, 17 rho values), ragged grid
     "coarse": lambda: with_rho_grid(cylinder_aperture("rc", 27, 1.0, 1.4, 10, 7, 45, mz=19), 17),
     # finer and graded, with columns inside the grid
     "graded": lambda: _graded(column_aperture("rg", 24, 1.0, [(0.13, -0.41), (0.0, 0.25),
                                                               (1.7, 0.3)], 9, 30, mz=20), 53),
+    # non-uniform sensor radii, the rho axis tied to them (uneven midpoint cells)
+    "graded_radii": lambda: _graded_radii(cylinder_aperture("rr", 21, 1.0, 1.3, 8, 6, 37,
+                                                             mz=17)),
 }
 _CACHE = {}
 
@@ -72,7 +81,8 @@ CASES = [(n, b) for n in sorted(APERTURES) for b in ("constant", "linear")]
 def test_operators_on_own_rho_grid_match_oracle(name, basis):
     ap, a12s, a34 = _operators(name, basis)
     plan = _plan(ap, basis=basis)
-    assert plan.info["n_rho"] == ap.n_rho != ap.n_radii
+    assert plan.info["n_rho"] == ap.n_rho
+    assert (ap.n_rho != ap.n_radii) == (ap.rho is not None)
     h = ap.dxy
     r, c, v = plan.export_coo(0)
     A = sp.csr_matrix((v, (r, c)), shape=(ap.n_angles * ap.n_rho, ap.ms ** 2))

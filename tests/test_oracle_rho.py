@@ -57,6 +57,23 @@ def test_rows_match_sampling_on_own_rho_grid(kind):
             assert np.abs(bf - a34[h * ap.n_radii + l]).max() <= 4 * r * np.pi / n, (h, l)
 
 
+def test_rows_match_sampling_for_graded_radii():
+    """Non-uniform sensor radii with the tied grid: uneven midpoint cells."""
+    ap0 = cylinder_aperture("t", 8, 1.0, 1.2, 3, 4, 15, l_max=3.0)
+    u = np.arange(1, 16) / 15
+    ap = dataclasses.replace(ap0, radii=3.0 * u ** 1.7)
+    a12s, a34 = geo.assemble_all(ap)
+    n = 1 << 20
+    A, c = a12s[2].toarray(), ap.column_centers[2]
+    for m, r in enumerate(ap.radii):
+        assert np.abs(brute.sampled_a12_row(ap, c, r, n) - A[m]).max() <= 4 * r * 2 * np.pi / n
+    a34 = a34.toarray()
+    for h in range(ap.n_z):
+        for l, r in enumerate(ap.radii):
+            bf = brute.sampled_a34_row(ap, ap.zpos[h], r, n)
+            assert np.abs(bf - a34[h * ap.n_radii + l]).max() <= 4 * r * np.pi / n, (h, l)
+
+
 def test_matches_sampled_discrete_operator_on_own_rho_grid():
     ap = _nonuniform(cylinder_aperture("t", 12, 1.0, 1.5, 4, 5, 24, l_max=3.5), 17)
     a12s, a34 = geo.assemble_all(ap)
