@@ -25,12 +25,13 @@ Prints one JSON line on stdout. Besides throughput it reports:
                 results (default run only)
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--weights f32|bf16|f16]
-                    [--basis constant|linear] [--n-rho N]
+                    [--basis constant|linear] [--n-rho N] [--aperture cylinder|square]
 
---basis linear and --n-rho N (a stage-2 radial grid of N values instead of the
-radii) measure the same workload on the widened operators; those runs report
-no cpu_baseline (the linear-basis oracle takes hours at this size) and no
-traffic (the counters were taken on the default operators).
+--basis linear, --n-rho N (a stage-2 radial grid of N values instead of the
+radii) and --aperture square (the columns spaced along a square instead of
+the cylinder) measure the same workload on the widened operators; those runs
+report no cpu_baseline and no traffic (the counters were taken on the default
+operators).
 """
 from __future__ import annotations
 
@@ -173,6 +174,9 @@ def main():
     p.add_argument("--basis", default="constant", choices=["constant", "linear"])
     p.add_argument("--n-rho", type=int, default=0,
                    help="stage-2 radial grid of this many values (0: the radii)")
+    p.add_argument("--aperture", default="cylinder", choices=["cylinder", "square"],
+                   help="square: the same columns spaced along a square of half-side R "
+                        "(columns anywhere) instead of the cylinder")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--profile-copy", action="store_true",
                    help="also run one 1 GiB read + 1 GiB write kernel (torch.neg; counter "
@@ -183,14 +187,16 @@ def main():
               "angle-sharded path is design only", file=sys.stderr)
         sys.exit(2)
 
-    from srt_inputs import config, phantoms, with_rho_grid
+    from srt_inputs import config, phantoms, square_columns, with_rho_grid
 
-    variant = args.basis != "constant" or args.n_rho > 0
+    variant = args.basis != "constant" or args.n_rho > 0 or args.aperture != "cylinder"
     ap = config(args.workload)
     t0 = time.perf_counter()
     F64 = phantoms.phantom(ap)
     if args.n_rho > 0:
         ap = with_rho_grid(ap, args.n_rho)
+    if args.aperture == "square":
+        ap = square_columns(ap, ap.radius)
     log(f"phantom {time.perf_counter() - t0:.1f} s")
     F_in = F64.astype(np.float32).astype(np.float64)  # the values the GPU receives
     cpu = None
@@ -293,7 +299,7 @@ def main():
                                                         if args.workload == "pact256" else
                                                         "128^3 on [-1,1]^3, R=1.3, 128 x 128 x 512"),
                    "batch": 1, "weights": args.weights, "phantom": "seeded",
-                   "basis": args.basis, "n_rho": info["n_rho"],
+                   "basis": args.basis, "n_rho": info["n_rho"], "aperture": args.aperture,
                    "nnz_a12": nnz12, "nnz_a34": nnz34, "plan_build_s": round(t_plan, 3)},
         "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved,
                      "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",

@@ -5,6 +5,6 @@ radii), voxel grids and phantoms. It contains none of the transform's
 arithmetic, so that the HIP path and the FP64 oracle can both consume the same
 arrays without sharing any code that computes the method.
 """
-from .configs import (Aperture, column_aperture, cylinder_aperture, config, with_rho_grid,  # noqa: F401
-                      CONFIG_NAMES)
+from .configs import (Aperture, column_aperture, cylinder_aperture, config, square_columns,  # noqa: F401
+                      with_rho_grid, CONFIG_NAMES)
 from . import phantoms  # noqa: F401

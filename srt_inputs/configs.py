@@ -123,6 +123,26 @@ def with_rho_grid(ap: Aperture, n_rho: int, rho_max: float | None = None) -> Ape
     return replace(ap, name=f"{ap.name}_rho{n_rho}", rho=rho)
 
 
+def square_columns(ap: Aperture, half_side: float) -> Aperture:
+    """The same grid, heights and radii with the N_a sensor columns placed
+    evenly along the perimeter of the square [-s, s]^2 (s = half_side)
+    instead of on a circle: columns anywhere (Sec. 2 only needs z-parallel
+    lines), at the size of a given workload."""
+    n, s = ap.n_angles, float(half_side)
+    t = 8.0 * s * (np.arange(n, dtype=np.float64) + 0.5) / n  # arc length along the perimeter
+    side, u = np.divmod(t, 2.0 * s)
+    u = u - s
+    # counter-clockwise: side 0 x = s, y = u; side 1 y = s, x = -u;
+    # side 2 x = -s, y = -u; side 3 y = -s, x = u
+    xy = np.empty((n, 2))
+    sides = [(np.full(n, s), u), (-u, np.full(n, s)), (np.full(n, -s), -u), (u, np.full(n, -s))]
+    for k, (x, y) in enumerate(sides):
+        sel = side == k
+        xy[sel, 0], xy[sel, 1] = x[sel], y[sel]
+    return replace(ap, name=f"{ap.name}_square", radius=float("nan"),
+                   angles=np.arctan2(xy[:, 1], xy[:, 0]), centers=xy)
+
+
 def column_aperture(name: str, m: int, half_width: float, centers, n_z: int, n_radii: int,
                     l_max: float | None = None, mz: int | None = None) -> Aperture:
     """Cubic grid [-W, W]^3 with sensor columns at arbitrary (x, y) positions

@@ -336,6 +336,39 @@ def test_tangent_circles_match_oracle():
     assert abs(B - a34[:, :live * ap.mz]).max() <= 1e-12 * h
 
 
+def test_pact256_square_columns_sampled():
+    """At 256^3 with the 512 columns spaced along a square instead of the
+    cylinder (the bench's --aperture square): sampled forward outputs and the
+    adjoint of data on two columns against the oracle (FP32 plan)."""
+    from srt_inputs import square_columns
+    ap0 = config("pact256")
+    ap = square_columns(ap0, ap0.radius)
+    F = _t(phantoms.phantom(ap0), torch.float32)
+    Fin = _np(F)
+    plan = _plan(ap, "f32")
+    Y = _np(plan.forward(F))
+    cols, heights = [0, 130, 333], [40, 220]
+    a34 = geo.assemble_a34(ap, heights=heights)
+    a12 = {a: geo.assemble_a12_at(ap, ap.column_centers[a]) for a in cols}
+    for a in cols:
+        G = osrt.stage1(a12[a], Fin).reshape(-1)
+        for h in heights:
+            rows = a34[h * ap.n_radii:(h + 1) * ap.n_radii]
+            assert rel_l2(Y[a, h], rows @ G) <= 1e-5, (a, h)
+    data = np.zeros(ap.data_shape)
+    rng = np.random.default_rng(2007)
+    for a in cols[:2]:
+        for h in heights:
+            data[a, h] = rng.standard_normal(ap.n_radii)
+    dt = _t(data, torch.float32)
+    Fp = _np(plan.adjoint(dt))
+    din = _np(dt)
+    ref = np.zeros(ap.vol_shape)
+    for a in cols[:2]:
+        ref += osrt.adj_stage1(a12[a], osrt.adj_stage2(a34, din[a], ap.mz), ap.ms)
+    assert rel_l2(Fp, ref) <= 1e-5
+
+
 # ------------------------------------------------------------------ columns anywhere
 COLUMN_SETS = {
     # a linear array below the grid, and a scatter with columns inside the
