@@ -9,6 +9,7 @@
 // transpose hold bit-identical weights.
 #include <hipcub/hipcub.hpp>
 
+#include <algorithm>
 #include <cmath>
 
 #include "srt_internal.h"
@@ -76,13 +77,16 @@ __global__ void row_pointers(const uint64_t *__restrict__ keys, int64_t n, uint6
 }
 
 // Largest radius index (plus one) among the pieces of the stacked A12, whose
-// keys are (a * nl + l) * npix + col.
+// keys are (a * nl + l) * npix + col. Grid-stride; the maximum is taken per
+// wavefront first, so only one lane per wavefront touches the shared counter.
 __global__ void live_kernel(const uint64_t *__restrict__ keys, int64_t n, uint64_t npix, int nl,
                             int *__restrict__ live) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const uint64_t row = keys[i] / npix;
-  atomicMax(live, (int)(row % (uint64_t)nl) + 1);
+  int m = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    m = max(m, (int)((keys[i] / npix) % (uint64_t)nl) + 1);
+  for (int o = warpSize / 2; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o));
+  if ((threadIdx.x & (warpSize - 1)) == 0 && m > 0) atomicMax(live, m);
 }
 
 // Renumbers rows a * nl + l (l < live) as a * live + l.
@@ -248,7 +252,8 @@ Status compact_a12(Coo *pieces, int32_t nl, int64_t npix, hipStream_t s, int32_t
   if (d.alloc(sizeof(int)) != hipSuccess) return fail(SRT_ENOMEM, "allocation failed");
   SRT_HIP(hipMemsetAsync(d.p, 0, sizeof(int), s));
   if (pieces->n > 0)
-    hipLaunchKernelGGL(live_kernel, dim3(blocks_for(pieces->n, 256)), dim3(256), 0, s,
+    hipLaunchKernelGGL(live_kernel, dim3((unsigned)std::min<int64_t>(blocks_for(pieces->n, 256), 8192)),
+                       dim3(256), 0, s,
                        pieces->keys, pieces->n, (uint64_t)npix, (int)nl, d.as<int>());
   SRT_HIP(hipGetLastError());
   int h = 0;

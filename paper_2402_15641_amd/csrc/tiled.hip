@@ -108,58 +108,76 @@ __global__ void k_ustart(const uint64_t *__restrict__ ukeys, int64_t nu, int64_t
 
 // Greedy cut of each block's distinct columns (ascending) into chunks with at
 // most kC columns and at most max_ent entries once every quad's rows are
-// padded to the quad's longest segment. One thread per block; per-slot counts
-// and per-quad maxima of the open chunk live in LDS.
-constexpr int kChunkThreads = 32;
+// padded to the quad's longest segment. One wavefront per block: lane l holds
+// the open chunk's entry counts of slots l*SPL .. l*SPL+SPL-1 in registers; the
+// lanes of a quad agree on its longest segment by shuffles, and the padded
+// entries a column adds are summed over the wavefront. A column that breaks a
+// limit closes the chunk and opens a new one holding it alone (that always
+// fits: at most one entry per row, so at most kQ padded entries per quad).
+constexpr int kChunkThreads = 64;
+constexpr int kSPL = kRB / kChunkThreads;  // slots per lane
+static_assert(kRB % kChunkThreads == 0 && (kSPL == 2 || kSPL == 4) && kQ == 4,
+              "a quad spans two lanes (two slots each) or one lane (four slots)");
 __global__ __launch_bounds__(kChunkThreads) void k_chunking(
     const int64_t *__restrict__ ustart, const int32_t *__restrict__ ucount,
     const int64_t *__restrict__ upos, const uint8_t *__restrict__ slot_sorted, int64_t nblk,
     int max_ent, int32_t *__restrict__ uchunk, int32_t *__restrict__ ulocal,
     int64_t *__restrict__ nch) {
-  __shared__ uint16_t cnt_all[kChunkThreads][kRB];
-  __shared__ uint16_t qmax_all[kChunkThreads][kNQ];
-  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b > nblk) return;
+  const int64_t b = blockIdx.x;
+  const int lane = threadIdx.x;
   if (b == nblk) {
-    nch[b] = 0;
+    if (lane == 0) nch[b] = 0;
     return;
   }
-  uint16_t *cnt = cnt_all[threadIdx.x];
-  uint16_t *qmax = qmax_all[threadIdx.x];
-  for (int i = 0; i < kRB; ++i) cnt[i] = 0;
-  for (int i = 0; i < kNQ; ++i) qmax[i] = 0;
+  int cnt[kSPL];
+#pragma unroll
+  for (int t = 0; t < kSPL; ++t) cnt[t] = 0;
+  int qmax = 0;  // longest segment of this lane's quad in the open chunk
+  // the quad's padded entries are counted by its first lane only
+  const bool quad_lead = kSPL == 4 || (lane & 1) == 0;
   int32_t chunk = 0, ncol = 0, padded = 0;
-  for (int64_t j = ustart[b]; j < ustart[b + 1]; ++j) {
-    // Add column j to the open chunk; if that breaks a limit, close the chunk
-    // and open a new one holding column j alone (that always fits: at most
-    // one entry per row, so at most kQ padded entries per touched quad).
-    bool again = true;
-    while (again) {
-      again = false;
-      int add = 0;
-      for (int64_t i = upos[j]; i < upos[j] + ucount[j]; ++i) {
-        const int sl = slot_sorted[i], q = sl / kQ;
-        const int c1 = ++cnt[sl];
-        if (c1 > qmax[q]) {
-          add += kQ * (c1 - qmax[q]);
-          qmax[q] = (uint16_t)c1;
-        }
+  const int64_t j0 = ustart[b], j1 = ustart[b + 1];
+  for (int64_t j = j0; j < j1; ++j) {
+    const int64_t e0 = upos[j];
+    const int n = ucount[j];
+    for (;;) {
+      int nc[kSPL];
+#pragma unroll
+      for (int t = 0; t < kSPL; ++t) nc[t] = cnt[t];
+      for (int i = 0; i < n; ++i) {
+        const int sl = slot_sorted[e0 + i];
+#pragma unroll
+        for (int t = 0; t < kSPL; ++t) nc[t] += sl == lane * kSPL + t;
       }
+      int m = nc[0];
+#pragma unroll
+      for (int t = 1; t < kSPL; ++t) m = max(m, nc[t]);
+      if (kSPL == 2) m = max(m, __shfl_xor(m, 1));
+      int add = quad_lead && m > qmax ? kQ * (m - qmax) : 0;
+#pragma unroll
+      for (int o = kChunkThreads / 2; o > 0; o >>= 1) add += __shfl_xor(add, o);
       if (ncol > 0 && (ncol + 1 > kC || padded + add > max_ent)) {
-        for (int i = 0; i < kRB; ++i) cnt[i] = 0;
-        for (int i = 0; i < kNQ; ++i) qmax[i] = 0;
+#pragma unroll
+        for (int t = 0; t < kSPL; ++t) cnt[t] = 0;
+        qmax = 0;
         ++chunk;
         ncol = 0;
         padded = 0;
-        again = true;
-      } else {
-        padded += add;
+        continue;  // the column again, alone in the new chunk
       }
+#pragma unroll
+      for (int t = 0; t < kSPL; ++t) cnt[t] = nc[t];
+      qmax = max(qmax, m);
+      padded += add;
+      break;
     }
-    uchunk[j] = chunk;
-    ulocal[j] = ncol++;
+    if (lane == 0) {
+      uchunk[j] = chunk;
+      ulocal[j] = ncol;
+    }
+    ++ncol;
   }
-  nch[b] = ustart[b + 1] > ustart[b] ? chunk + 1 : 0;
+  if (lane == 0) nch[b] = j1 > j0 ? chunk + 1 : 0;
 }
 
 __global__ void k_chunk_cols(const uint64_t *__restrict__ ukeys, int64_t nu,
@@ -376,7 +394,7 @@ Status build_tiled(const Csr &m, const RowGrid &g, int max_ent, hipStream_t s, T
   // 2. chunks
   hipLaunchKernelGGL(k_ustart, dim3(nblocks(nblk + 1, t)), dim3(t), 0, s, ukeys.as<uint64_t>(), nu,
                      nblk, ustart.as<int64_t>());
-  hipLaunchKernelGGL(k_chunking, dim3(nblocks(nblk + 1, kChunkThreads)), dim3(kChunkThreads), 0, s,
+  hipLaunchKernelGGL(k_chunking, dim3((unsigned)(nblk + 1)), dim3(kChunkThreads), 0, s,
                      ustart.as<int64_t>(), ucount.as<int32_t>(), upos.as<int64_t>(),
                      slot_sorted.as<uint8_t>(), nblk, max_ent, uchunk.as<int32_t>(),
                      ulocal.as<int32_t>(), nch.as<int64_t>());
