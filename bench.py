@@ -14,24 +14,27 @@ Prints one JSON line on stdout. Besides throughput it reports:
                 v_fmac_f32 at that rate, packed FP32 is disabled in this build);
                 `traffic` comes from the committed rocprofv3 counter summary
                 when it was taken on the current kernel source, else null
-  hbm           compulsory bytes of a pair (operators once, input, output)
-                over the pair time, against 8 TB/s
+  hbm           compulsory bytes of a step (operators once, inputs, outputs)
+                over the step time, against 8 TB/s
   cpu_baseline  the FP64 oracle timed on the host on a bounded sample of the
                 same workload and scaled to one pair: one core, and beside it
                 ("parallel") one process per host core, split by column
-  step_ms       mean, median and minimum of the timed steps (value = 1/mean)
+  step_ms       mean, median and minimum of the timed steps (value =
+                batch/mean)
   bf16_weights  the same pair with BF16-stored weights (FP32 values and
                 accumulation): rate and relative L2 distance from the FP32-weight
                 results (default run only)
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--weights f32|bf16|f16]
                     [--basis constant|linear] [--n-rho N] [--aperture cylinder|square]
+                    [--batch B]
 
 --basis linear, --n-rho N (a stage-2 radial grid of N values instead of the
 radii) and --aperture square (the columns spaced along a square instead of
-the cylinder) measure the same workload on the widened operators; those runs
-report no cpu_baseline and no traffic (the counters were taken on the default
-operators).
+the cylinder) measure the same workload on the widened operators; --batch B
+applies B volumes per call (value still counts pairs). Those runs report no
+cpu_baseline and no traffic (the counters were taken on the default operators
+at batch 1).
 """
 from __future__ import annotations
 
@@ -177,6 +180,8 @@ def main():
     p.add_argument("--aperture", default="cylinder", choices=["cylinder", "square"],
                    help="square: the same columns spaced along a square of half-side R "
                         "(columns anywhere) instead of the cylinder")
+    p.add_argument("--batch", type=int, default=1,
+                   help="volumes per apply (the phantom repeated); value stays pairs/s")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--profile-copy", action="store_true",
                    help="also run one 1 GiB read + 1 GiB write kernel (torch.neg; counter "
@@ -189,7 +194,11 @@ def main():
 
     from srt_inputs import config, phantoms, square_columns, with_rho_grid
 
-    variant = args.basis != "constant" or args.n_rho > 0 or args.aperture != "cylinder"
+    if args.batch < 1:
+        p.error("--batch must be at least 1")
+    nb = args.batch
+    variant = (args.basis != "constant" or args.n_rho > 0 or args.aperture != "cylinder"
+               or nb != 1)
     ap = config(args.workload)
     t0 = time.perf_counter()
     F64 = phantoms.phantom(ap)
@@ -213,6 +222,8 @@ def main():
         log("bench.py needs a ROCm device")
         sys.exit(1)
     vol = torch.from_numpy(F64).float().cuda()
+    if nb > 1:
+        vol = vol.expand((nb,) + tuple(vol.shape)).contiguous()
 
     t0 = time.perf_counter()
     plan = SRTPlan.from_geometry(ap, value_dtype="f32", weight_dtype=args.weights,
@@ -221,9 +232,10 @@ def main():
     t_plan = time.perf_counter() - t0
     info = plan.info
     log(f"plan {t_plan:.2f} s {info}")
-    ws = plan.workspace(1)
-    data = torch.empty(ap.data_shape, device="cuda")
-    back = torch.empty(ap.vol_shape, device="cuda")
+    lead = (nb,) if nb > 1 else ()
+    ws = plan.workspace(nb)
+    data = torch.empty(lead + tuple(ap.data_shape), device="cuda")
+    back = torch.empty(lead + tuple(ap.vol_shape), device="cuda")
     stream = torch.cuda.current_stream()
 
     if args.profile_copy:
@@ -259,10 +271,10 @@ def main():
     # Algorithmic FLOPs per launch of each sparse stage (2 per multiply-add).
     nnz12, nnz34 = info["nnz_a12"], info["nnz_a34"]
     stages = {
-        "stage1_fwd": (fwd_ms[1], 2.0 * nnz12 * ap.mz),
-        "stage2_fwd": (fwd_ms[3], 2.0 * nnz34 * ap.n_angles),
-        "stage2_adj": (adj_ms[1], 2.0 * nnz34 * ap.n_angles),
-        "stage1_adj": (adj_ms[3], 2.0 * nnz12 * ap.mz),
+        "stage1_fwd": (fwd_ms[1], 2.0 * nnz12 * ap.mz * nb),
+        "stage2_fwd": (fwd_ms[3], 2.0 * nnz34 * ap.n_angles * nb),
+        "stage2_adj": (adj_ms[1], 2.0 * nnz34 * ap.n_angles * nb),
+        "stage1_adj": (adj_ms[3], 2.0 * nnz12 * ap.mz * nb),
     }
     dom = max(stages, key=lambda k: stages[k][0])
     dom_ms, dom_flop = stages[dom]
@@ -278,12 +290,12 @@ def main():
 
     wb = {"f32": 4, "bf16": 2, "f16": 2}[args.weights]
     op_bytes = 2 * (nnz12 + nnz34) * (4 + wb)  # operator and its transpose, once each
-    io_bytes = 2 * 4 * (int(np.prod(ap.vol_shape)) + int(np.prod(ap.data_shape)))
+    io_bytes = 2 * 4 * nb * (int(np.prod(ap.vol_shape)) + int(np.prod(ap.data_shape)))
     hbm_gbps = (op_bytes + io_bytes) / (ms_per_step * 1e-3) / 1e9
 
     result = {
         "metric": METRIC,
-        "value": 1000.0 / ms_per_step,
+        "value": 1000.0 * nb / ms_per_step,
         "unit": "pairs/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -298,14 +310,14 @@ def main():
                                                         "512 columns x 256 heights x 1024 radii"
                                                         if args.workload == "pact256" else
                                                         "128^3 on [-1,1]^3, R=1.3, 128 x 128 x 512"),
-                   "batch": 1, "weights": args.weights, "phantom": "seeded",
+                   "batch": nb, "weights": args.weights, "phantom": "seeded",
                    "basis": args.basis, "n_rho": info["n_rho"], "aperture": args.aperture,
                    "nnz_a12": nnz12, "nnz_a34": nnz34, "plan_build_s": round(t_plan, 3)},
         "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved,
                      "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_VALU_TFLOPS, "traffic": traffic,
                      "launch_ms": dom_ms, "flop_per_launch": dom_flop},
-        "hbm": {"compulsory_bytes_per_pair": op_bytes + io_bytes, "achieved_gbps": hbm_gbps,
+        "hbm": {"compulsory_bytes_per_step": op_bytes + io_bytes, "achieved_gbps": hbm_gbps,
                 "peak_gbps": PEAK_HBM_GBPS, "frac": hbm_gbps / PEAK_HBM_GBPS,
                 "measured_stage_gbps": measured or None},
         "step_ms": {"mean": ms_per_step, "median": float(np.median(steps_ms)),
