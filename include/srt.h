@@ -200,10 +200,13 @@ srt_status srt_plan_create_desc(const srt_plan_desc *desc, void *hip_stream, srt
  *              (overwritten)
  *   batch      >= 1
  *   workspace  device scratch of at least the size srt_plan_footprint
- *              reports, or NULL to use the plan's own (then calls on one plan
- *              must not overlap)
+ *              reports, 16-byte aligned (hipMalloc's alignment is best), or
+ *              NULL to use the plan's own (then calls on one plan must not
+ *              overlap)
  *   workspace_bytes  size of workspace (ignored when workspace is NULL)
- * Errors: EINVAL, ENOMEM (own workspace), EDEVICE.
+ * vol and data must be aligned to the size of value_dtype.
+ * Errors: EINVAL (NULL or misaligned arrays, batch < 1, workspace too small),
+ * ENOMEM (own workspace), EDEVICE.
  */
 srt_status srt_forward(srt_plan *plan, const void *vol, void *data, int32_t batch,
                        void *workspace, size_t workspace_bytes, void *hip_stream);
@@ -281,13 +284,14 @@ srt_status srt_plan_stage_times(const srt_plan *plan, int32_t adjoint, int32_t n
  *   resid      host array of (n_iter + 1) * batch doubles, or NULL:
  *              resid[k * batch + b] = ||A^T (g - A f_k)||_2 of item b
  *              (the call then returns after the stream has finished)
- *   workspace  device scratch of at least srt_cgls_workspace() bytes (not
- *              shared with concurrent calls)
+ *   workspace  device scratch of at least srt_cgls_workspace() bytes,
+ *              16-byte aligned (not shared with concurrent calls)
+ *   vol and data must be aligned to the size of value_dtype.
  * Inner products are reduced in FP64 in a fixed order; step lengths stay on
  * the device (no host round trip per iteration). Asynchronous on hip_stream
  * unless resid is given.
- * Errors: EINVAL (NULL pointers, batch or n_iter out of range, workspace too
- * small), EDEVICE.
+ * Errors: EINVAL (NULL or misaligned pointers, batch or n_iter out of range,
+ * workspace too small), EDEVICE.
  */
 srt_status srt_cgls(srt_plan *plan, void *vol, const void *data, int32_t batch,
                     int32_t n_iter, double *resid, void *workspace,

@@ -721,6 +721,14 @@ Status apply(srt_plan *p, const void *in, void *out, int32_t B, void *ws, size_t
   if (!p || p->magic != kPlanMagic) return fail(SRT_EINVAL, "plan is NULL or not a live plan");
   if (!in || !out) return fail(SRT_EINVAL, "NULL input or output");
   if (B <= 0) return fail(SRT_EINVAL, "batch must be >= 1");
+  // The layout passes read and write the caller's arrays element by element
+  // (16 bytes at a time where aligned); the stage kernels copy and store the
+  // workspace buffers in 16-byte pieces.
+  const size_t esz = dtype_size(p->vdtype);
+  if (reinterpret_cast<uintptr_t>(in) % esz != 0 || reinterpret_cast<uintptr_t>(out) % esz != 0)
+    return fail(SRT_EINVAL, "input and output must be aligned to their element size");
+  if (ws && reinterpret_cast<uintptr_t>(ws) % 16 != 0)
+    return fail(SRT_EINVAL, "workspace must be 16-byte aligned");
   const Geometry &g = p->geo;
   if ((int64_t)B * g.mz > INT32_MAX / 4 || (int64_t)B * g.na > INT32_MAX / 4)
     return fail(SRT_ENOTSUP, "batch too large");

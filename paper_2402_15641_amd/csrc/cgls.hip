@@ -235,6 +235,12 @@ srt_status srt_cgls(srt_plan *plan, void *vol, const void *data, int32_t batch, 
   const Layout L = layout(plan, batch, n_iter);
   if (!workspace || workspace_bytes < L.total)
     return fail(SRT_EINVAL, "workspace is NULL or smaller than srt_cgls_workspace reports").code;
+  // workspace vectors are read and written 16 bytes at a time
+  if ((uintptr_t)workspace % 16 != 0)
+    return fail(SRT_EINVAL, "workspace must be 16-byte aligned").code;
+  const size_t esz = plan->vdtype == SRT_F64 ? 8 : 4;
+  if ((uintptr_t)vol % esz != 0 || (uintptr_t)data % esz != 0)
+    return fail(SRT_EINVAL, "volume and data must be aligned to their element size").code;
   DeviceScope ds(plan->device);
   if (ds.err != hipSuccess) return hip_fail(ds.err, "hipSetDevice").code;
   hipStream_t st = (hipStream_t)hip_stream;

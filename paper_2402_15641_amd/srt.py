@@ -7,6 +7,7 @@ shapes and dtypes and allocates outputs.
 """
 from __future__ import annotations
 
+import numpy as np
 import torch
 
 from . import binding as B
@@ -93,6 +94,19 @@ class SRTPlan:
             raise ValueError(f"{name} must have shape [B,]{tuple(shape)}, got {tuple(t.shape)}")
         return 1 if t.dim() == len(shape) else t.shape[0]
 
+    def _check_out(self, out: torch.Tensor, shape, batch: int, name: str):
+        # the library writes `batch` items: a smaller output would be overrun
+        if self._check(out, shape, name) != batch:
+            raise ValueError(f"{name} must hold {batch} item(s) of shape {tuple(shape)}, "
+                             f"got {tuple(out.shape)}")
+
+    def _check_workspace(self, ws):
+        # passed on as a raw device pointer and byte count
+        if ws is None:
+            return
+        if not isinstance(ws, torch.Tensor) or ws.device != self.device or not ws.is_contiguous():
+            raise ValueError(f"workspace must be a contiguous tensor on {self.device}")
+
     def forward(self, vol: torch.Tensor, out: torch.Tensor | None = None, workspace=None,
                 stream=None) -> torch.Tensor:
         batch = self._check(vol, self.vol_shape, "vol")
@@ -100,7 +114,8 @@ class SRTPlan:
         if out is None:
             out = torch.empty(shape, dtype=self.dtype, device=self.device)
         else:
-            self._check(out, self.data_shape, "out")
+            self._check_out(out, self.data_shape, batch, "out")
+        self._check_workspace(workspace)
         if batch > 0:
             B.srt_forward(self.handle, vol, out, batch, workspace, stream)
         return out
@@ -112,7 +127,8 @@ class SRTPlan:
         if out is None:
             out = torch.empty(shape, dtype=self.dtype, device=self.device)
         else:
-            self._check(out, self.vol_shape, "out")
+            self._check_out(out, self.vol_shape, batch, "out")
+        self._check_workspace(workspace)
         if batch > 0:
             B.srt_adjoint(self.handle, data, out, batch, workspace, stream)
         return out
@@ -135,8 +151,11 @@ class SRTPlan:
         if vol0 is None:
             f = torch.zeros(shape, dtype=self.dtype, device=self.device)
         else:
-            self._check(vol0, self.vol_shape, "vol0")
+            self._check_out(vol0, self.vol_shape, batch, "vol0")
             f = vol0.clone()
+        if batch == 0:
+            return f, (np.zeros((int(n_iter) + 1, 0)) if want_resid else None)
+        self._check_workspace(workspace)
         if workspace is None:
             workspace = torch.empty(B.srt_cgls_workspace(self.handle, batch, n_iter),
                                     dtype=torch.uint8, device=self.device)

@@ -196,6 +196,76 @@ def test_batch_and_workspace_are_bitwise_stable():
     assert e.value.status == SRT_EINVAL
 
 
+def test_wrapper_rejects_outputs_and_workspaces_it_cannot_use():
+    """The torch wrapper refuses an output (or CGLS start) holding another
+    number of items than the input, and a workspace that is not a contiguous
+    tensor on the plan's device, before the library is called; a batch of
+    one is accepted with or without its batch axis, and an empty CGLS batch
+    returns at once."""
+    ap, _, _ = operators("grid32")
+    plan = _plan(ap, "f32")
+    vols = _t(np.random.default_rng(6).uniform(0, 1, (3,) + ap.vol_shape), torch.float32)
+    data = torch.zeros((3,) + ap.data_shape, device="cuda")
+    for bad in ((2,) + ap.data_shape, ap.data_shape, (4,) + ap.data_shape):
+        with pytest.raises(ValueError, match="item"):
+            plan.forward(vols, out=torch.empty(bad, device="cuda"))
+    with pytest.raises(ValueError, match="item"):
+        plan.adjoint(data, out=torch.empty(ap.vol_shape, device="cuda"))
+    with pytest.raises(ValueError, match="item"):
+        plan.cgls(data, 1, vol0=torch.zeros(ap.vol_shape, device="cuda"))
+    ws = plan.workspace(3)
+    for bad in (ws.cpu(), ws[::2]):
+        with pytest.raises(ValueError, match="workspace"):
+            plan.forward(vols, workspace=bad)
+        with pytest.raises(ValueError, match="workspace"):
+            plan.adjoint(data, workspace=bad)
+    with pytest.raises(ValueError, match="workspace"):
+        plan.cgls(data, 1, workspace=ws.cpu())
+    Y1 = plan.forward(vols[0])
+    out = torch.empty((1,) + ap.data_shape, device="cuda")
+    assert torch.equal(plan.forward(vols[0], out=out)[0], Y1)
+    out = torch.empty(ap.data_shape, device="cuda")
+    assert torch.equal(plan.forward(vols[:1], out=out), Y1)
+    f, r = plan.cgls(torch.zeros((0,) + ap.data_shape, device="cuda"), 2)
+    assert f.shape == (0,) + ap.vol_shape and r.shape == (3, 0)
+
+
+def test_misaligned_arrays_are_rejected():
+    """A caller workspace off 16-byte alignment, or a volume or data array off
+    its element size, is an argument error caught before anything runs (apply
+    and CGLS); a 16-byte offset is accepted and gives the same result."""
+    from paper_2402_15641_amd import binding as B
+    ap, _, _ = operators("grid32")
+    plan = _plan(ap, "f32")
+    L = B.lib()
+    vol = _t(np.random.default_rng(4).uniform(0, 1, ap.vol_shape), torch.float32)
+    data = torch.zeros(ap.data_shape, device="cuda")
+    n = plan.workspace(1).numel()
+    big = torch.zeros(n + 64, dtype=torch.uint8, device="cuda")
+    for off in (4, 8):
+        st = L.srt_forward(plan.handle, vol.data_ptr(), data.data_ptr(), 1,
+                           big.data_ptr() + off, n, None)
+        assert st == B.SRT_EINVAL and "aligned" in B.srt_last_error()
+    st = L.srt_adjoint(plan.handle, data.data_ptr(), vol.data_ptr() + 2, 1, None, 0, None)
+    assert st == B.SRT_EINVAL and "aligned" in B.srt_last_error()
+    st = L.srt_forward(plan.handle, vol.data_ptr() + 1, data.data_ptr(), 1, None, 0, None)
+    assert st == B.SRT_EINVAL and "aligned" in B.srt_last_error()
+    Y0 = plan.forward(vol)
+    torch.cuda.synchronize()
+    st = L.srt_forward(plan.handle, vol.data_ptr(), data.data_ptr(), 1, big.data_ptr() + 16, n,
+                       None)
+    torch.cuda.synchronize()
+    assert st == B.SRT_OK and torch.equal(data, Y0)
+    nb = B.srt_cgls_workspace(plan.handle, 1, 2)
+    cw = torch.zeros(nb + 64, dtype=torch.uint8, device="cuda")
+    st = L.srt_cgls(plan.handle, vol.data_ptr(), data.data_ptr(), 1, 2, None, cw.data_ptr() + 8,
+                    nb, None)
+    assert st == B.SRT_EINVAL and "aligned" in B.srt_last_error()
+    st = L.srt_cgls(plan.handle, vol.data_ptr() + 2, data.data_ptr(), 1, 2, None, cw.data_ptr(),
+                    nb, None)
+    assert st == B.SRT_EINVAL and "aligned" in B.srt_last_error()
+
+
 # ------------------------------------------------------------------ grid128
 @pytest.fixture(scope="module")
 def grid128():
