@@ -6,5 +6,5 @@ arithmetic, so that the HIP path and the FP64 oracle can both consume the same
 arrays without sharing any code that computes the method.
 """
 from .configs import (Aperture, column_aperture, cylinder_aperture, config, square_columns,  # noqa: F401
-                      with_rho_grid, CONFIG_NAMES)
+                      random_aperture, with_rho_grid, CONFIG_NAMES)
 from . import phantoms  # noqa: F401
