@@ -161,20 +161,21 @@ def column_aperture(name: str, m: int, half_width: float, centers, n_z: int, n_r
                     radii=ap.radii, centers=c)
 
 
-def random_aperture(seed: int) -> Aperture:
+def random_aperture(seed: int, scale: int = 1) -> Aperture:
     """A small seeded geometry off every regular case, for parity sweeps:
     a grid that is not centred, with voxels that are not cubes (dz != dxy);
     1-7 columns, on a circle of random radius (inside or outside the grid)
     or scattered anywhere; 1-6 heights and 1-25 radii, unevenly spaced; and
-    for one seed in three a stage-2 radial grid of its own."""
+    for one seed in three a stage-2 radial grid of its own. scale > 1
+    multiplies the largest grid and sample counts (more operator tiles)."""
     rng = np.random.default_rng(seed)
-    ms, mz = int(rng.integers(2, 31)), int(rng.integers(1, 21))
+    ms, mz = int(rng.integers(2, 30 * scale + 1)), int(rng.integers(1, 20 * scale + 1))
     dxy = float(rng.uniform(0.5, 1.5))
     dz = dxy * float(rng.uniform(0.6, 1.7))
     x0 = -0.5 * ms * dxy + float(rng.uniform(-2.0, 2.0)) * dxy
     z0 = -0.5 * mz * dz + float(rng.uniform(-2.0, 2.0)) * dz
     half = 0.5 * ms * dxy
-    n_cols = int(rng.integers(1, 8))
+    n_cols = int(rng.integers(1, 7 * scale + 1))
     if rng.uniform() < 0.5:
         R = half * float(rng.uniform(0.3, 1.6))
         ang = np.sort(rng.uniform(0.0, 2.0 * np.pi, n_cols))
@@ -182,7 +183,7 @@ def random_aperture(seed: int) -> Aperture:
     else:
         xy = rng.uniform(-1.5 * half, 1.5 * half, (n_cols, 2))
     zlo, zhi = z0 - dz, z0 + (mz + 1) * dz
-    zpos = np.sort(rng.uniform(zlo, zhi, int(rng.integers(1, 7))))
+    zpos = np.sort(rng.uniform(zlo, zhi, int(rng.integers(1, 6 * scale + 1))))
     # farthest grid corner from any column, over the height range
     cx = np.array([x0, x0 + ms * dxy])
     far_xy = max(float(np.hypot(np.max(np.abs(cx - c[0])), np.max(np.abs(cx - c[1]))))
@@ -195,9 +196,9 @@ def random_aperture(seed: int) -> Aperture:
             if n == 1 or np.min(np.diff(v)) > 1e-6 * hi:
                 return v
 
-    radii = increasing(int(rng.integers(1, 26)), l_max)
-    rho = increasing(int(rng.integers(1, 31)), 1.05 * l_max) if rng.uniform() < 1 / 3 else None
-    return Aperture(name=f"random{seed}", ms=ms, mz=mz, x0=x0, z0=z0, dxy=dxy, dz=dz,
+    radii = increasing(int(rng.integers(1, 25 * scale + 1)), l_max)
+    rho = increasing(int(rng.integers(1, 30 * scale + 1)), 1.05 * l_max) if rng.uniform() < 1 / 3 else None
+    return Aperture(name=f"random{seed}" + (f"x{scale}" if scale > 1 else ""), ms=ms, mz=mz, x0=x0, z0=z0, dxy=dxy, dz=dz,
                     radius=float("nan"), angles=np.arctan2(xy[:, 1], xy[:, 0]), zpos=zpos,
                     radii=radii, centers=xy, rho=rho)
 
