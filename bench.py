@@ -24,6 +24,10 @@ Prints one JSON line on stdout. Besides throughput it reports:
   bf16_weights  the same pair with BF16-stored weights (FP32 values and
                 accumulation): rate and relative L2 distance from the FP32-weight
                 results (default run only)
+  serving       p50/p99 latency and throughput of a mixed stream of forward
+                and adjoint requests on 64^3/128^3/192^3 grids at 1000 req/s,
+                FP32 and BF16 weights, with the device-bound capacity of each
+                (default run only; --no-serving skips it)
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--weights f32|bf16|f16]
                     [--basis constant|linear] [--n-rho N] [--aperture cylinder|square]
@@ -167,6 +171,27 @@ def cpu_baseline(ap, F64, n_cols=32, h_stride=8, max_procs=16):
                      "threads_env": threads_env}}
 
 
+def serving_leg(rate=1000.0, seconds=2.0):
+    """p50/p99 latency and throughput of the mixed serving stream at one
+    arrival rate, FP32 and BF16 weights (the full rate sweep is
+    paper_2402_15641_amd.serve_bench)."""
+    from paper_2402_15641_amd.serve_bench import serving_mix
+    t0 = time.perf_counter()
+    recs = serving_mix([rate], seconds=seconds, pool=2)
+    out = {"workload": "grids 64^3/128^3/192^3 drawn uniformly, N x N x 4N apertures, 70% "
+                       "forward / 30% adjoint, Poisson arrivals, batches of up to 8 on 4 "
+                       "streams, admission by device-memory footprint (16 GiB)",
+           "rate_rps": rate, "requests": int(rate * seconds)}
+    for r in recs:
+        w = out.setdefault(r["weights"], {})
+        if "device_bound_capacity_rps" in r:
+            w["capacity_rps"] = r["device_bound_capacity_rps"]
+        else:
+            w.update({k: r[k] for k in ("p50_ms", "p99_ms", "mean_ms", "throughput_rps")})
+    log(f"serving leg {time.perf_counter() - t0:.1f} s")
+    return out
+
+
 def main():
     p = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     p.add_argument("--gpus", type=int, default=1)
@@ -183,6 +208,8 @@ def main():
     p.add_argument("--batch", type=int, default=1,
                    help="volumes per apply (the phantom repeated); value stays pairs/s")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-serving", action="store_true",
+                   help="skip the serving leg (the mixed request stream at 1000 req/s)")
     p.add_argument("--profile-copy", action="store_true",
                    help="also run one 1 GiB read + 1 GiB write kernel (torch.neg; counter "
                         "calibration for FETCH_SIZE / WRITE_SIZE)")
@@ -348,6 +375,8 @@ def main():
             "rel_l2_adjoint_vs_f32_weights": float((b16 - back).norm() / back.norm())}
         p16.close()
     plan.close()
+    if not variant and not args.no_serving:
+        result["serving"] = serving_leg()
     print(json.dumps(result), flush=True)
 
 
