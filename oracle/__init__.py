@@ -19,9 +19,12 @@ Contents (each function cites the passage of the paper it follows):
   linear        both CRT matrices for a piecewise-linear (tent) voxel basis,
                 by exact arc splitting and Gauss-Legendre quadrature per piece
                 (Sec. 3.1: the method holds for other bases)
+  nnls          nonnegative least squares with the matched pair (accelerated
+                projected gradient) and the power estimate of ||A||^2 that
+                sets its step
 
 Precision: float64 throughout. Every function here is pinned by a
 -m "not gpu" test against something other than itself (closed forms,
 brute-force sampling, invariants, symmetries); see tests/test_oracle_*.py.
 """
-from . import geometry, srt, closed_forms, brute, cgls, linear  # noqa: F401
+from . import geometry, srt, closed_forms, brute, cgls, linear, nnls  # noqa: F401
