@@ -301,6 +301,62 @@ srt_status srt_cgls(srt_plan *plan, void *vol, const void *data, int32_t batch,
 srt_status srt_cgls_workspace(const srt_plan *plan, int32_t batch, int32_t n_iter,
                               size_t *bytes);
 
+/*
+ * srt_nnls -- nonnegative least squares with the matched pair:
+ * min 0.5 ||A f - g||_2^2 subject to f >= 0 (an initial pressure is never
+ * negative), by n_iter iterations of accelerated projected gradient (FISTA,
+ * Beck and Teboulle, SIAM J. Imaging Sci. 2009, Sec. 4, the projection onto
+ * f >= 0 as its proximal step). A is srt_forward (Alg. 1), A^T srt_adjoint
+ * (Alg. 2); the gradient A^T (A f - g) is only correct because the adjoint
+ * is matched (Sec. 1, Sec. 3.2). With y_1 = f_0 and t_1 = 1, step k is
+ *   f_k = max(0, y_k - step * A^T (A y_k - g)),
+ *   t_{k+1} = (1 + sqrt(1 + 4 t_k^2)) / 2,
+ *   y_{k+1} = f_k + ((t_k - 1) / t_{k+1}) (f_k - f_{k-1}).
+ * Each batch item is its own problem.
+ *   vol        device [batch][mz][ms][ms]: f_0 on entry (need not be
+ *              nonnegative), f_{n_iter} on return
+ *   data       device [batch][n_angles][n_z][n_radii]: g (read only)
+ *   batch      1 .. 65535
+ *   n_iter     >= 0
+ *   step       1/L with L >= ||A||_2^2 (finite, > 0); srt_opnorm2 estimates
+ *              ||A||_2^2 from below, so scale its estimate up a little
+ *   resid      host array of n_iter * batch doubles, or NULL:
+ *              resid[k * batch + b] = ||A y_{k+1} - g||_2 of item b, the
+ *              misfit where step k + 1 took its gradient (the call then
+ *              returns after the stream has finished)
+ *   workspace  device scratch of at least srt_nnls_workspace() bytes,
+ *              16-byte aligned (not shared with concurrent calls)
+ *   vol and data must be aligned to the size of value_dtype.
+ * Misfits are reduced in FP64 in a fixed order. Asynchronous on hip_stream
+ * unless resid is given.
+ * Errors: EINVAL (NULL or misaligned pointers, batch, n_iter or step out of
+ * range, workspace too small), EDEVICE.
+ */
+srt_status srt_nnls(srt_plan *plan, void *vol, const void *data, int32_t batch,
+                    int32_t n_iter, double step, double *resid, void *workspace,
+                    size_t workspace_bytes, void *hip_stream);
+
+/* Workspace bytes srt_nnls needs for `batch` items and `n_iter` iterations. */
+srt_status srt_nnls_workspace(const srt_plan *plan, int32_t batch, int32_t n_iter,
+                              size_t *bytes);
+
+/*
+ * srt_opnorm2 -- estimate of ||A||_2^2, the largest eigenvalue of A^T A,
+ * by n_iter steps of the power method on A^T A (srt_forward then
+ * srt_adjoint) from the all-ones volume, renormalising after each step.
+ * A has no negative entries, so the dominant eigenvector of A^T A can be
+ * taken nonnegative and the start has a component along it.
+ *   norm2      host; receives the Rayleigh quotient ||A v||^2 / ||v||^2 of
+ *              the last iterate v (0 when n_iter is 0). It never exceeds
+ *              ||A||_2^2 and rises towards it. The call waits for the stream.
+ *   workspace  device scratch of at least srt_nnls_workspace(plan, 1, 0)
+ *              bytes, 16-byte aligned
+ * Errors: EINVAL (NULL norm2, n_iter < 0, workspace too small or
+ * misaligned), EDEVICE.
+ */
+srt_status srt_opnorm2(srt_plan *plan, int32_t n_iter, double *norm2, void *workspace,
+                       size_t workspace_bytes, void *hip_stream);
+
 /* Thread-local description of the last error on the calling thread. */
 const char *srt_last_error(void);
 

@@ -25,7 +25,7 @@ BASES = {"constant": 0, "linear": 1}
 SYMBOLS = ("srt_plan_create", "srt_plan_create_columns", "srt_plan_create_desc", "srt_forward", "srt_adjoint", "srt_plan_destroy",
            "srt_plan_footprint", "srt_plan_get_info", "srt_plan_export_coo",
            "srt_plan_set_timing", "srt_plan_stage_times", "srt_cgls", "srt_cgls_workspace",
-           "srt_last_error")
+           "srt_nnls", "srt_nnls_workspace", "srt_opnorm2", "srt_last_error")
 STAGES = 5
 
 
@@ -89,6 +89,9 @@ def lib() -> ctypes.CDLL:
                                        ctypes.POINTER(I32)]
     L.srt_cgls.argtypes = [P, P, P, I32, I32, P, P, SZ, P]
     L.srt_cgls_workspace.argtypes = [P, I32, I32, ctypes.POINTER(SZ)]
+    L.srt_nnls.argtypes = [P, P, P, I32, I32, D, P, P, SZ, P]
+    L.srt_nnls_workspace.argtypes = [P, I32, I32, ctypes.POINTER(SZ)]
+    L.srt_opnorm2.argtypes = [P, I32, ctypes.POINTER(D), P, SZ, P]
     for name in SYMBOLS[:-1]:
         getattr(L, name).restype = ctypes.c_int
     L.srt_last_error.argtypes = []
@@ -269,3 +272,33 @@ def srt_cgls(plan: int, vol, data, batch: int, n_iter: int, workspace, want_resi
                           workspace.numel() * workspace.element_size(), _stream_ptr(stream)),
            "srt_cgls")
     return resid
+
+
+def srt_nnls_workspace(plan: int, batch: int, n_iter: int) -> int:
+    """Workspace bytes srt_nnls needs (batch 1, n_iter 0: what srt_opnorm2 needs)."""
+    b = ctypes.c_size_t()
+    _check(lib().srt_nnls_workspace(plan, int(batch), int(n_iter), ctypes.byref(b)),
+           "srt_nnls_workspace")
+    return b.value
+
+
+def srt_nnls(plan: int, vol, data, batch: int, n_iter: int, step: float, workspace,
+             want_resid=True, stream=None):
+    """n_iter FISTA steps for min ||A f - g||^2, f >= 0, in place on vol;
+    returns the misfits ||A y_k - g|| as an (n_iter, batch) array, or None
+    when want_resid is False (then the call is asynchronous)."""
+    resid = np.zeros((int(n_iter), int(batch)), np.float64) if want_resid else None
+    _check(lib().srt_nnls(plan, vol.data_ptr(), data.data_ptr(), int(batch), int(n_iter),
+                          float(step), None if resid is None else resid.ctypes.data,
+                          workspace.data_ptr(), workspace.numel() * workspace.element_size(),
+                          _stream_ptr(stream)), "srt_nnls")
+    return resid
+
+
+def srt_opnorm2(plan: int, n_iter: int, workspace, stream=None) -> float:
+    """Power-method estimate of ||A||_2^2 after n_iter steps (waits for the stream)."""
+    out = ctypes.c_double()
+    _check(lib().srt_opnorm2(plan, int(n_iter), ctypes.byref(out), workspace.data_ptr(),
+                             workspace.numel() * workspace.element_size(), _stream_ptr(stream)),
+           "srt_opnorm2")
+    return out.value

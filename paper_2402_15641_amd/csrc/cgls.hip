@@ -12,8 +12,24 @@
 // reduced in FP64 in a fixed order (so runs are bitwise repeatable), and the
 // step lengths are read by the update kernels from device memory, so an
 // iteration never waits for the host.
+//
+// Nonnegative least squares, min 0.5 ||A f - g||^2 subject to f >= 0, by
+// accelerated projected gradient (FISTA; Beck and Teboulle 2009, Sec. 4, the
+// projection onto f >= 0 as the proximal step), with a fixed step 1/L,
+// L >= ||A||^2:
+//   y_1 = f_0, t_1 = 1
+//   f_k = max(0, y_k - (1/L) A^T (A y_k - g))
+//   y_{k+1} = f_k + ((t_k - 1)/t_{k+1}) (f_k - f_{k-1}),
+//   t_{k+1} = (1 + sqrt(1 + 4 t_k^2)) / 2
+// The weights do not depend on the data and are computed on the host; one
+// fused kernel does the projection and the extrapolation. ||A||^2, the
+// largest eigenvalue of A^T A, is estimated by power iteration from the
+// all-ones volume (A has no negative entries, so the dominant eigenvector of
+// A^T A can be taken nonnegative and the start overlaps it).
+#include <cmath>
 #include <cstdint>
 #include <utility>
+#include <vector>
 
 #include "srt_internal.h"
 
@@ -211,6 +227,162 @@ Status run(srt_plan *plan, T *f, const T *g, int32_t B, int32_t n_iter, double *
   return Status{};
 }
 
+// One FISTA step after the gradient s = A^T (g - A y) (note the sign: the
+// residual kernel forms g - A y), flat over the whole batch:
+//   x = y + step * s;  f_new = max(0, x) (NaN stays NaN);
+//   y = f_new + beta * (f_new - f);  f = f_new
+template <typename T, bool VEC>
+__global__ void k_fista(T *__restrict__ f, T *__restrict__ y, const T *__restrict__ s, T step,
+                        T beta, int64_t n) {
+  auto one = [&](T &fv, T &yv, T sv) {
+    const T x = yv + step * sv;
+    const T fn = x < (T)0 ? (T)0 : x;
+    yv = fn + beta * (fn - fv);
+    fv = fn;
+  };
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  if constexpr (VEC) {
+    using VT = typename V<T>::t;
+    constexpr int W = V<T>::n;
+    VT *fv = reinterpret_cast<VT *>(f), *yv = reinterpret_cast<VT *>(y);
+    const VT *sv = reinterpret_cast<const VT *>(s);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n / W; i += stride) {
+      VT a = fv[i], c = yv[i];
+      const VT d = sv[i];
+      T *as = reinterpret_cast<T *>(&a), *cs = reinterpret_cast<T *>(&c);
+      const T *ds = reinterpret_cast<const T *>(&d);
+#pragma unroll
+      for (int k = 0; k < W; ++k) one(as[k], cs[k], ds[k]);
+      fv[i] = a;
+      yv[i] = c;
+    }
+  } else {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+      one(f[i], y[i], s[i]);
+  }
+}
+
+template <typename T>
+__global__ void k_fill(T *__restrict__ v, T val, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    v[i] = val;
+}
+
+// v = w / sqrt(nw[0]) (zero when nw[0] is zero)
+template <typename T>
+__global__ void k_normalize(T *__restrict__ v, const T *__restrict__ w,
+                            const double *__restrict__ nw, int64_t n) {
+  const double d = nw[0];
+  const T inv = d > 0.0 ? (T)(1.0 / sqrt(d)) : (T)0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    v[i] = w[i] * inv;
+}
+
+struct NnlsLayout {
+  size_t r, s, y, ws, scal, part, hist, total;  // byte offsets
+  size_t ws_bytes;
+};
+
+NnlsLayout nnls_layout(const srt_plan *p, int32_t batch, int32_t n_iter) {
+  const Geometry &g = p->geo;
+  const size_t es = dtype_size(p->vdtype);
+  const size_t vol = (size_t)batch * g.mz * g.ms * g.ms * es;
+  const size_t dat = (size_t)batch * g.na * g.nh * g.nl * es;
+  NnlsLayout L{};
+  size_t o = 0;
+  L.r = o; o += align_up(dat);
+  L.s = o; o += align_up(vol);
+  L.y = o; o += align_up(vol);
+  L.ws_bytes = workspace_bytes(p, batch);
+  L.ws = o; o += align_up(L.ws_bytes);
+  L.scal = o; o += align_up(sizeof(double) * 3 * batch);
+  L.part = o; o += align_up(sizeof(double) * kRedBlocks * batch);
+  L.hist = o; o += align_up(sizeof(double) * (size_t)(n_iter > 0 ? n_iter : 1) * batch);
+  L.total = o;
+  return L;
+}
+
+template <typename T>
+Status dot_into(const T *x, const T *y, int64_t n, int32_t B, bool vec, double *part, double *out,
+                double *h, hipStream_t st) {
+  if (vec)
+    hipLaunchKernelGGL((k_dot_partial<T, true>), dim3(kRedBlocks, B), dim3(kRedThreads), 0, st, x, y, n, part);
+  else
+    hipLaunchKernelGGL((k_dot_partial<T, false>), dim3(kRedBlocks, B), dim3(kRedThreads), 0, st, x, y, n, part);
+  hipLaunchKernelGGL(k_dot_final, dim3((B + 63) / 64), dim3(64), 0, st, part, B, out, h);
+  SRT_HIP(hipGetLastError());
+  return Status{};
+}
+
+template <typename T>
+Status run_nnls(srt_plan *plan, T *f, const T *g, int32_t B, int32_t n_iter, double step,
+                double *resid, char *w, const NnlsLayout &L, hipStream_t st) {
+  const Geometry &geo = plan->geo;
+  const int64_t nv = (int64_t)geo.mz * geo.ms * geo.ms, nd = (int64_t)geo.na * geo.nh * geo.nl;
+  T *r = (T *)(w + L.r), *s = (T *)(w + L.s), *y = (T *)(w + L.y);
+  void *ws = w + L.ws;
+  double *part = (double *)(w + L.part), *hist = (double *)(w + L.hist);
+  double *scal = (double *)(w + L.scal);
+  constexpr int W = V<T>::n;
+  const bool dv = nd % W == 0;
+  const bool fv = (nv * B) % W == 0 && (uintptr_t)f % 16 == 0;
+  SRT_HIP(hipMemcpyAsync(y, f, sizeof(T) * nv * B, hipMemcpyDeviceToDevice, st));
+  double t = 1.0;
+  for (int k = 0; k < n_iter; ++k) {
+    const double t_next = (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;
+    const double beta = (t - 1.0) / t_next;
+    t = t_next;
+    SRT_TRY(apply_plan(plan, y, r, B, ws, L.ws_bytes, st, false));  // r = A y
+    hipLaunchKernelGGL(k_rsub<T>, dim3(grid_for(nd * B)), dim3(256), 0, st, r, g, nd * B);
+    SRT_HIP(hipGetLastError());                                        // r = g - A y
+    SRT_TRY(dot_into<T>(r, r, nd, B, dv, part, scal, hist + (size_t)k * B, st));
+    SRT_TRY(apply_plan(plan, r, s, B, ws, L.ws_bytes, st, true));   // s = A^T (g - A y)
+    const dim3 grid(grid_for(fv ? nv * B / W : nv * B));
+    if (fv)
+      hipLaunchKernelGGL((k_fista<T, true>), grid, dim3(256), 0, st, f, y, s, (T)step, (T)beta, nv * B);
+    else
+      hipLaunchKernelGGL((k_fista<T, false>), grid, dim3(256), 0, st, f, y, s, (T)step, (T)beta, nv * B);
+    SRT_HIP(hipGetLastError());
+  }
+  if (resid) {
+    if (n_iter > 0)
+      SRT_HIP(hipMemcpyAsync(resid, hist, sizeof(double) * (size_t)n_iter * B,
+                             hipMemcpyDeviceToHost, st));
+    SRT_HIP(hipStreamSynchronize(st));
+  }
+  return Status{};
+}
+
+template <typename T>
+Status run_opnorm2(srt_plan *plan, int32_t n_iter, double *norm2, char *w, const NnlsLayout &L,
+                   hipStream_t st) {
+  const Geometry &geo = plan->geo;
+  const int64_t nv = (int64_t)geo.mz * geo.ms * geo.ms, nd = (int64_t)geo.na * geo.nh * geo.nl;
+  T *u = (T *)(w + L.r), *wv = (T *)(w + L.s), *v = (T *)(w + L.y);
+  void *ws = w + L.ws;
+  double *part = (double *)(w + L.part), *sc = (double *)(w + L.scal);
+  constexpr int W = V<T>::n;
+  const bool vv = nv % W == 0, dv = nd % W == 0;
+  hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(nv)), dim3(256), 0, st, v, (T)1, nv);
+  SRT_HIP(hipGetLastError());
+  for (int k = 0; k < n_iter; ++k) {
+    SRT_TRY(apply_plan(plan, v, u, 1, ws, L.ws_bytes, st, false));   // u = A v
+    SRT_TRY(dot_into<T>(u, u, nd, 1, dv, part, sc, nullptr, st));    // ||A v||^2
+    SRT_TRY(dot_into<T>(v, v, nv, 1, vv, part, sc + 1, nullptr, st));  // ||v||^2
+    SRT_TRY(apply_plan(plan, u, wv, 1, ws, L.ws_bytes, st, true));   // w = A^T A v
+    SRT_TRY(dot_into<T>(wv, wv, nv, 1, vv, part, sc + 2, nullptr, st));
+    hipLaunchKernelGGL(k_normalize<T>, dim3(grid_for(nv)), dim3(256), 0, st, v, wv, sc + 2, nv);
+    SRT_HIP(hipGetLastError());
+  }
+  double h[2] = {0.0, 0.0};
+  if (n_iter > 0) SRT_HIP(hipMemcpyAsync(h, sc, sizeof(h), hipMemcpyDeviceToHost, st));
+  SRT_HIP(hipStreamSynchronize(st));
+  *norm2 = h[1] > 0.0 ? h[0] / h[1] : 0.0;
+  return Status{};
+}
+
 }  // namespace
 }  // namespace srt
 
@@ -248,6 +420,62 @@ srt_status srt_cgls(srt_plan *plan, void *vol, const void *data, int32_t batch, 
   if (plan->vdtype == SRT_F64)
     return run<double>(plan, (double *)vol, (const double *)data, batch, n_iter, resid, w, L, st).code;
   return run<float>(plan, (float *)vol, (const float *)data, batch, n_iter, resid, w, L, st).code;
+}
+
+srt_status srt_nnls_workspace(const srt_plan *plan, int32_t batch, int32_t n_iter, size_t *bytes) {
+  using namespace srt;
+  if (!plan || plan->magic != kPlanMagic) return fail(SRT_EINVAL, "plan is NULL or not a live plan").code;
+  if (!bytes || batch <= 0 || batch > 65535 || n_iter < 0)
+    return fail(SRT_EINVAL, "bytes must be non-NULL, batch in [1, 65535] and n_iter >= 0").code;
+  *bytes = nnls_layout(plan, batch, n_iter).total;
+  return SRT_OK;
+}
+
+srt_status srt_nnls(srt_plan *plan, void *vol, const void *data, int32_t batch, int32_t n_iter,
+                    double step, double *resid, void *workspace, size_t workspace_bytes,
+                    void *hip_stream) {
+  using namespace srt;
+  if (!plan || plan->magic != kPlanMagic) return fail(SRT_EINVAL, "plan is NULL or not a live plan").code;
+  if (!vol || !data) return fail(SRT_EINVAL, "NULL volume or data").code;
+  if (batch <= 0 || batch > 65535 || n_iter < 0)
+    return fail(SRT_EINVAL, "batch must be in [1, 65535] and n_iter >= 0").code;
+  if (!(std::isfinite(step) && step > 0.0))
+    return fail(SRT_EINVAL, "step must be finite and > 0").code;
+  const NnlsLayout L = nnls_layout(plan, batch, n_iter);
+  if (!workspace || workspace_bytes < L.total)
+    return fail(SRT_EINVAL, "workspace is NULL or smaller than srt_nnls_workspace reports").code;
+  if ((uintptr_t)workspace % 16 != 0)
+    return fail(SRT_EINVAL, "workspace must be 16-byte aligned").code;
+  const size_t esz = plan->vdtype == SRT_F64 ? 8 : 4;
+  if ((uintptr_t)vol % esz != 0 || (uintptr_t)data % esz != 0)
+    return fail(SRT_EINVAL, "volume and data must be aligned to their element size").code;
+  DeviceScope ds(plan->device);
+  if (ds.err != hipSuccess) return hip_fail(ds.err, "hipSetDevice").code;
+  hipStream_t st = (hipStream_t)hip_stream;
+  char *w = (char *)workspace;
+  if (plan->vdtype == SRT_F64)
+    return run_nnls<double>(plan, (double *)vol, (const double *)data, batch, n_iter, step, resid,
+                            w, L, st).code;
+  return run_nnls<float>(plan, (float *)vol, (const float *)data, batch, n_iter, step, resid, w,
+                         L, st).code;
+}
+
+srt_status srt_opnorm2(srt_plan *plan, int32_t n_iter, double *norm2, void *workspace,
+                       size_t workspace_bytes, void *hip_stream) {
+  using namespace srt;
+  if (!plan || plan->magic != kPlanMagic) return fail(SRT_EINVAL, "plan is NULL or not a live plan").code;
+  if (!norm2 || n_iter < 0) return fail(SRT_EINVAL, "norm2 must be non-NULL and n_iter >= 0").code;
+  const NnlsLayout L = nnls_layout(plan, 1, 0);
+  if (!workspace || workspace_bytes < L.total)
+    return fail(SRT_EINVAL, "workspace is NULL or smaller than srt_nnls_workspace(plan, 1, 0)").code;
+  if ((uintptr_t)workspace % 16 != 0)
+    return fail(SRT_EINVAL, "workspace must be 16-byte aligned").code;
+  DeviceScope ds(plan->device);
+  if (ds.err != hipSuccess) return hip_fail(ds.err, "hipSetDevice").code;
+  hipStream_t st = (hipStream_t)hip_stream;
+  char *w = (char *)workspace;
+  if (plan->vdtype == SRT_F64) return run_opnorm2<double>(plan, n_iter, norm2, w, L, st).code;
+  return run_opnorm2<float>(plan, n_iter, norm2, w, L, st).code;
 }
 
 }  // extern "C"

@@ -162,6 +162,44 @@ class SRTPlan:
         resid = B.srt_cgls(self.handle, f, data, batch, n_iter, workspace, want_resid, stream)
         return f, resid
 
+    def opnorm2(self, n_iter: int = 30, workspace=None, stream=None) -> float:
+        """Power-method estimate of ||A||_2^2 (largest eigenvalue of A^T A),
+        a lower bound that rises towards it with n_iter."""
+        self._check_workspace(workspace)
+        if workspace is None:
+            workspace = torch.empty(B.srt_nnls_workspace(self.handle, 1, 0), dtype=torch.uint8,
+                                    device=self.device)
+        return B.srt_opnorm2(self.handle, n_iter, workspace, stream)
+
+    def nnls(self, data: torch.Tensor, n_iter: int, step: float | None = None,
+             vol0: torch.Tensor | None = None, workspace=None, want_resid: bool = True,
+             stream=None, power_iters: int = 30, margin: float = 1.05):
+        """Nonnegative least squares min ||A f - data||^2, f >= 0: n_iter
+        FISTA iterations from vol0 (zeros if None). Without a step, the step
+        is 1 / (margin * opnorm2(power_iters)). Returns (f, misfits
+        ||A y_k - data|| per iteration and batch item, step used)."""
+        batch = self._check(data, self.data_shape, "data")
+        shape = self.vol_shape if data.dim() == 3 else (batch,) + self.vol_shape
+        if vol0 is None:
+            f = torch.zeros(shape, dtype=self.dtype, device=self.device)
+        else:
+            self._check_out(vol0, self.vol_shape, batch, "vol0")
+            f = vol0.clone()
+        self._check_workspace(workspace)
+        if step is None:
+            L = self.opnorm2(power_iters, stream=stream)
+            if not L > 0:
+                raise ValueError("the operator is zero: no step can be derived")
+            step = 1.0 / (margin * L)
+        if batch == 0:
+            return f, (np.zeros((int(n_iter), 0)) if want_resid else None), step
+        if workspace is None:
+            workspace = torch.empty(B.srt_nnls_workspace(self.handle, batch, n_iter),
+                                    dtype=torch.uint8, device=self.device)
+        resid = B.srt_nnls(self.handle, f, data, batch, n_iter, step, workspace, want_resid,
+                           stream)
+        return f, resid, step
+
     def export_coo(self, which: int):
         return B.srt_plan_export_coo(self.handle, which)
 

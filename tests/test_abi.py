@@ -15,7 +15,7 @@ HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "sr
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(srt_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(srt_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_header_and_binding_agree():
@@ -80,6 +80,11 @@ def test_null_plan_calls():
     assert L.srt_cgls(None, None, None, 1, 1, None, None, 0, None) == B.SRT_EINVAL
     assert "plan" in B.srt_last_error()
     assert L.srt_cgls_workspace(None, 1, 1, ctypes.byref(r)) == B.SRT_EINVAL
+    assert L.srt_nnls(None, None, None, 1, 1, 1.0, None, None, 0, None) == B.SRT_EINVAL
+    assert "plan" in B.srt_last_error()
+    assert L.srt_nnls_workspace(None, 1, 1, ctypes.byref(r)) == B.SRT_EINVAL
+    d = ctypes.c_double()
+    assert L.srt_opnorm2(None, 1, ctypes.byref(d), None, 0, None) == B.SRT_EINVAL
 
 
 def test_create_columns_rejects_bad_positions():
