@@ -205,6 +205,10 @@ srt_status srt_plan_create_desc(const srt_plan_desc *desc, void *hip_stream, srt
  *              overlap)
  *   workspace_bytes  size of workspace (ignored when workspace is NULL)
  * vol and data must be aligned to the size of value_dtype.
+ * With a caller workspace and stage timing off, the call only launches
+ * kernels on hip_stream (no allocation, memset, copy or wait), so it can be
+ * captured into a HIP graph and replayed; the plan's own workspace may be
+ * allocated on first use and cannot.
  * Errors: EINVAL (NULL or misaligned arrays, batch < 1, workspace too small),
  * ENOMEM (own workspace), EDEVICE.
  */

@@ -604,6 +604,23 @@ Status spmm(Stage st, const Tiled &m, const T *X, T *Y, int D, hipStream_t s) {
   return Status{};
 }
 
+// Clears an output with a kernel rather than a memset, so that an apply
+// captured into a HIP graph holds kernel nodes only.
+template <typename T>
+__global__ void k_zero(T *__restrict__ y, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = (T)0;
+}
+
+template <typename T>
+Status zero(T *y, int64_t n, hipStream_t s) {
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 8192);
+  if (blocks > 0) hipLaunchKernelGGL(k_zero<T>, dim3((unsigned)blocks), dim3(256), 0, s, y, n);
+  SRT_HIP(hipGetLastError());
+  return Status{};
+}
+
 // Records HIP events between stages when the plan is timing its applies.
 struct Marks {
   StageEvents *rec = nullptr;
@@ -633,7 +650,7 @@ Status forward_impl(srt_plan *p, const T *vol, T *data, int32_t B, T *P, T *Q, h
   const int D1 = B * g.mz, D2 = B * g.na;
   SRT_TRY(mk.at(0));
   if (L == 0) {  // no circle meets the grid: the transform is identically zero
-    SRT_HIP(hipMemsetAsync(data, 0, sizeof(T) * (size_t)B * g.na * NR, s));
+    SRT_TRY(zero<T>(data, (int64_t)B * g.na * NR, s));
     for (int i = 1; i <= kStages; ++i) SRT_TRY(mk.at(i));
     return Status{};
   }
@@ -666,7 +683,7 @@ Status adjoint_impl(srt_plan *p, const T *data, T *vol, int32_t B, T *P, T *Q, h
   const int D1 = B * g.mz, D2 = B * g.na;
   SRT_TRY(mk.at(0));
   if (L == 0) {
-    SRT_HIP(hipMemsetAsync(vol, 0, sizeof(T) * (size_t)B * g.mz * M2, s));
+    SRT_TRY(zero<T>(vol, (int64_t)B * g.mz * M2, s));
     for (int i = 1; i <= kStages; ++i) SRT_TRY(mk.at(i));
     return Status{};
   }
