@@ -197,10 +197,15 @@ class GpuExecutor:
     def next_event(self) -> Optional[float]:
         return None
 
+    # completions are found by polling events; a short sleep keeps the delay
+    # between a batch ending and its requests finishing near the sleep's own
+    # granularity on Linux (~50 us)
+    POLL_S = 5e-5
+
     def wait_until(self, t: float):
         dt = t - self.clock()
         if dt > 0:
-            time.sleep(min(dt, 2e-4))
+            time.sleep(min(dt, self.POLL_S))
 
 
 def serve(trace: List[Request], sched: Scheduler, ex, realtime: bool = True) -> List[Request]:
@@ -237,7 +242,7 @@ def serve(trace: List[Request], sched: Scheduler, ex, realtime: bool = True) -> 
         if nxt:
             ex.wait_until(min(nxt))
         elif realtime:
-            ex.wait_until(now + 1e-4)
+            ex.wait_until(now + 5e-5)
         else:
             raise RuntimeError("scheduler stalled with work left")
     return finished + sched.rejected
