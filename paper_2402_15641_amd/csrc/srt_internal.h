@@ -116,10 +116,17 @@ constexpr int kNW = SRT_WG_WAVES;  // wavefronts per workgroup
 // runs kQ consecutive slots in lockstep and a wavefront 4 * kQ, so
 // consecutive slots should be rows with the same amount of work per chunk. along_i1 numbers slots along i1
 // first (slot = r2 * b1 + r1), otherwise along i2 (slot = r1 * b2 + r2).
+//
+// Blocks are numbered in tiles of `tile` groups along i1: inside a tile the
+// i1 group steps fastest, then the i2 group, then the tile (tile 1: row-major
+// over (i1 group, i2 group)). The apply kernels deal consecutive block numbers
+// to the same XCD, so this picks which neighbouring blocks run side by side
+// and share staged dense rows through that XCD's L2.
 struct RowGrid {
   int64_t n1 = 0, n2 = 0;
   int64_t b1 = 0, b2 = 0;
   bool along_i1 = false;  // consecutive block slots step along i1 (else along i2)
+  int64_t tile = 1;       // i1 groups per tile of the block numbering
 };
 
 struct Tiled {

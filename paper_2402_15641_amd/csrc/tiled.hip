@@ -48,8 +48,10 @@ struct Buf {
 
 __device__ __forceinline__ void block_of(const RowGrid &g, int64_t row, int64_t *blk, int *slot) {
   const int64_t i1 = row / g.n2, i2 = row - i1 * g.n2;
-  const int64_t nb2 = (g.n2 + g.b2 - 1) / g.b2;
-  *blk = (i1 / g.b1) * nb2 + i2 / g.b2;
+  const int64_t nb1 = (g.n1 + g.b1 - 1) / g.b1, nb2 = (g.n2 + g.b2 - 1) / g.b2;
+  const int64_t q1 = i1 / g.b1, q2 = i2 / g.b2, t = q1 / g.tile;
+  const int64_t w = nb1 - t * g.tile < g.tile ? nb1 - t * g.tile : g.tile;  // last tile may be short
+  *blk = t * g.tile * nb2 + q2 * w + (q1 - t * g.tile);
   *slot = g.along_i1 ? (int)((i2 % g.b2) * g.b1 + i1 % g.b1) : (int)((i1 % g.b1) * g.b2 + i2 % g.b2);
 }
 
