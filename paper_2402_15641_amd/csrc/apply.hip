@@ -65,6 +65,15 @@ template <typename T> struct TileShape {
 // (slice-major) work order makes the blocks that run side by side on one XCD
 // neighbours in the operator, which share dense rows through that L2.
 constexpr int kXcds = 8;
+// Each XCD takes K consecutive work items, then jumps ahead by 8K, so that all
+// XCDs work on nearby blocks at once (ids past the last whole group of 8K keep
+// their hardware order).
+__device__ __forceinline__ int xcd_chunked(int id, int n, int K) {
+  const int G = kXcds * K, full = n / G * G;
+  if (id >= full) return id;
+  const int x = id % kXcds, k = id / kXcds;
+  return (k / K) * G + x * K + (k % K);
+}
 __device__ __forceinline__ int xcd_local(int id, int n) {
   const int x = id % kXcds, k = id / kXcds;
   const int q = n / kXcds, r = n % kXcds;
@@ -208,7 +217,9 @@ __device__ __forceinline__ void tiled_body(const int32_t *__restrict__ blk_rows,
   __shared__ uint32_t w0[L::WWORDS], w1[L::WWORDS];
   const L buf0{dense0, col0, w0}, buf1{dense1, col1, w1};
 
-  const int bid = remap ? xcd_local(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+  // remap < 0: a contiguous range per XCD; 0: hardware order; K > 0: chunks of K
+  const int bid = remap < 0 ? xcd_local(blockIdx.x, gridDim.x)
+                  : remap == 0 ? (int)blockIdx.x : xcd_chunked(blockIdx.x, gridDim.x, remap);
   const int blk = bid % nblk, slice = bid / nblk;
   const int d0 = slice * DW;
   const int tid = threadIdx.x;
@@ -578,10 +589,10 @@ Status spmm(Stage st, const Tiled &m, const T *X, T *Y, int D, hipStream_t s) {
   if (grid > INT32_MAX) return fail(SRT_ENOTSUP, "launch grid too large");
   const T scale = (T)(1.0 / m.scale);
   const WT *w = (const WT *)m.ent_w;
-  // XCD-local work order: measured to cut L2 misses for both forward stages
-  // and the stage-1 adjoint; the stage-2 adjoint's blocks share more when
-  // dealt round-robin.
-  const int remap = st != Stage::s2_adj;
+  // Work order over the XCDs, measured at 256^3: a contiguous range per XCD
+  // for both forward stages and the stage-1 adjoint; chunks of 16 for the
+  // stage-2 adjoint (5% faster than round-robin, 7-8% faster than ranges).
+  const int remap = st == Stage::s2_adj ? 16 : -1;
   // Buffer copies address the dense operand with 32-bit byte offsets.
   const uint64_t xb = (uint64_t)m.ncols * (uint64_t)D * sizeof(T);
   const int mode = D % TileShape<T>::VS != 0 ? 0 : (xb < (1ull << 32) ? 1 : 2);
