@@ -205,7 +205,7 @@ __device__ __forceinline__ void tiled_body(const int32_t *__restrict__ blk_rows,
                                            const int32_t *__restrict__ ent_col,
                                            const WT *__restrict__ ent_w, const T *__restrict__ X,
                                            T *__restrict__ Y, int nblk, int D, T scale,
-                                           int remap, uint32_t xbytes) {
+                                           int remap, int slice_inner, uint32_t xbytes) {
   constexpr bool VEC = MODE != 0, BUF = MODE == 1, PACKED = ChunkLds<T, WT>::PACKED;
   using S = TileShape<T>;
   using V16 = typename Vec16<T>::type;
@@ -220,7 +220,11 @@ __device__ __forceinline__ void tiled_body(const int32_t *__restrict__ blk_rows,
   // remap < 0: a contiguous range per XCD; 0: hardware order; K > 0: chunks of K
   const int bid = remap < 0 ? xcd_local(blockIdx.x, gridDim.x)
                   : remap == 0 ? (int)blockIdx.x : xcd_chunked(blockIdx.x, gridDim.x, remap);
-  const int blk = bid % nblk, slice = bid / nblk;
+  // work order: slices outermost (slice-major), or innermost (a block's
+  // slices consecutively, so its entries are re-read from L2)
+  const int nsl = (int)gridDim.x / nblk;
+  const int blk = slice_inner ? bid / nsl : bid % nblk;
+  const int slice = slice_inner ? bid % nsl : bid / nblk;
   const int d0 = slice * DW;
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -466,9 +470,9 @@ __device__ __forceinline__ void tiled_body(const int32_t *__restrict__ blk_rows,
       const int32_t *__restrict__ chunk_ent, const int32_t *__restrict__ qseg,                 \
       const int32_t *__restrict__ ent_col, const WT *__restrict__ ent_w,                       \
       const T *__restrict__ X, T *__restrict__ Y, int nblk, int D, T scale, int remap,         \
-      uint32_t xbytes) {                                                                       \
+      int slice_inner, uint32_t xbytes) {                                                      \
     tiled_body<T, WT, MODE>(blk_rows, blk_chunk, chunk_cols, chunk_ncols, chunk_ent, qseg,     \
-                            ent_col, ent_w, X, Y, nblk, D, scale, remap, xbytes);              \
+                            ent_col, ent_w, X, Y, nblk, D, scale, remap, slice_inner, xbytes); \
   }
 SRT_STAGE_KERNEL(stage1_fwd)  // A12_a applied to every slice: G = A12 F
 SRT_STAGE_KERNEL(stage2_fwd)  // A34 applied to every column: Y = A34 G
@@ -589,10 +593,12 @@ Status spmm(Stage st, const Tiled &m, const T *X, T *Y, int D, hipStream_t s) {
   if (grid > INT32_MAX) return fail(SRT_ENOTSUP, "launch grid too large");
   const T scale = (T)(1.0 / m.scale);
   const WT *w = (const WT *)m.ent_w;
-  // Work order over the XCDs, measured at 256^3: a contiguous range per XCD
-  // for both forward stages and the stage-1 adjoint; chunks of 16 for the
-  // stage-2 adjoint (5% faster than round-robin, 7-8% faster than ranges).
+  // Work order, measured at 256^3: a contiguous range per XCD for both
+  // forward stages and the stage-1 adjoint; chunks of 16 for the stage-2
+  // adjoint (5% faster than round-robin, 7-8% faster than ranges), which also
+  // runs a block's slices consecutively (2% faster; 13% slower for stage 1).
   const int remap = st == Stage::s2_adj ? 16 : -1;
+  const int slice_inner = st == Stage::s2_adj ? 1 : 0;
   // Buffer copies address the dense operand with 32-bit byte offsets.
   const uint64_t xb = (uint64_t)m.ncols * (uint64_t)D * sizeof(T);
   const int mode = D % TileShape<T>::VS != 0 ? 0 : (xb < (1ull << 32) ? 1 : 2);
@@ -600,7 +606,7 @@ Status spmm(Stage st, const Tiled &m, const T *X, T *Y, int D, hipStream_t s) {
   auto go = [&](auto kern) {
     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kNW * 64), 0, s, m.blk_rows, m.blk_chunk,
                        m.chunk_cols, m.chunk_ncols, m.chunk_ent, m.qseg, m.ent_col, w, X, Y,
-                       (int)m.nblk, D, scale, remap, xbytes);
+                       (int)m.nblk, D, scale, remap, slice_inner, xbytes);
   };
 #define SRT_GO(K)                                \
   (mode == 1 ? go(K<T, WT, 1>) : mode == 2 ? go(K<T, WT, 2>) : go(K<T, WT, 0>))
