@@ -172,19 +172,20 @@ Status create(const srt_grid *grid, int32_t basis, const double *col_xy, int32_t
   free_pieces();
   // Row-blocked copies for the applies: compact blocks of kRB rows whose
   // arcs share cells (at kRB = 128: 8 columns x 16 radii, 16 heights x 8
-  // radii, 8 x 16 rho-z cells, 8 x 16 pixels). Rows processed side by side get equal work per
-  // chunk: one radius at 8 columns (A12), one radius at 8 heights (A34), 8
-  // z-neighbouring cells (A34^T), 8 x-neighbouring pixels (A12^T). Block
-  // numbering tiles (measured at 256^3 over tiles of 1, 2, 3, 4 and 8):
-  // 2 column groups for A12, 2 height groups for A34, 4 rho groups for
-  // A34^T, plain row-major for A12^T.
+  // radii, 16 x 8 rho-z cells, 8 x 16 pixels). Rows processed side by side
+  // get equal work per chunk: one radius at 8 columns (A12), one radius at 8
+  // heights (A34), 4 rho-neighbouring cells at one z (A34^T), 4
+  // y-neighbouring pixels (A12^T). Shapes, slot order and block numbering
+  // tiles (2 column groups for A12, 2 height groups for A34, 4 rho groups
+  // for A34^T, plain row-major for A12^T) were measured at 256^3 under the
+  // kernels' work order.
   const int64_t L = p->live;
   const int me = vdt == SRT_F64 ? kE64 : kE32;
   const int64_t bh = kRB / 16;  // 16 or 8
   if (st.ok()) st = build_tiled(p->a12, RowGrid{na, L, 8, kRB / 8, true, 2}, me, s, &p->t12);
-  if (st.ok()) st = build_tiled(p->a12t, RowGrid{grid->ms, grid->ms, bh, 16, false, 1}, me, s, &p->t12t);
+  if (st.ok()) st = build_tiled(p->a12t, RowGrid{grid->ms, grid->ms, bh, 16, true, 1}, me, s, &p->t12t);
   if (st.ok()) st = build_tiled(p->a34, RowGrid{nh, nl, 16, bh, true, 2}, me, s, &p->t34);
-  if (st.ok()) st = build_tiled(p->a34t, RowGrid{L, grid->mz, bh, 16, false, 4}, me, s, &p->t34t);
+  if (st.ok()) st = build_tiled(p->a34t, RowGrid{L, grid->mz, 16, bh, true, 4}, me, s, &p->t34t);
   if (!st.ok()) return bail(st);
   p->magic = kPlanMagic;
   *out = p;
