@@ -231,8 +231,6 @@ size_t dtype_size(srt_dtype t) {
 
 using namespace srt;
 
-extern "C" {
-
 namespace {
 // Column positions of a cylinder aperture: column a stands at
 // (R cos angles[a], R sin angles[a]).
@@ -251,6 +249,8 @@ Status cylinder_columns(double cyl_radius, const double *angles, int32_t n_angle
   return Status{};
 }
 }  // namespace
+
+extern "C" {
 
 srt_status srt_plan_create(const srt_grid *grid, double cyl_radius, const double *angles,
                            int32_t n_angles, const double *z_pos, int32_t n_z,
