@@ -1,65 +1,81 @@
-"""Alg. 1 (forward) and Alg. 2 (matched adjoint) of the discrete SRT, FP64.
+"""The discrete SRT of a cylindrical aperture and its adjoint, FP64.
 
-Layouts: volume F[k][j][i] (z, y, x); data Y[a][h][l] (sensor column, sensor
-height, sphere radius, radius fastest). The paper states the per-column output
-once as N_h x N_l and once as N_l x N_h; the reading here is [h][l], matching
-the row order h N_l + l of A34.
+Test infrastructure: only the tests, the smoke check and the benchmark's CPU
+baseline call this module; the library never does.
 
-The full-aperture adjoint is the sum over columns of Alg. 2 applied to each
-column's data, which is exactly the transpose of the stacked forward.
+Sec. 2 factors the SRT of the sensors on one z-parallel column into two
+circular Radon transforms. CRT12 integrates the volume over circles about the
+column in every z-plane, giving an image f12 on the (rho, z) half-plane of
+that column; CRT34 integrates f12 over half circles about each sensor of the
+column. With the voxel basis of Sec. 3.1 both are sparse matrices
+(oracle.geometry): A12_a (N_rho x M_s^2) for column a, and A34
+(N_h N_l x N_rho M_z), the same for every column. So
+
+    SRT_a f = A34 vec(A12_a F),    F[p][k] = f at pixel p of slice k,
+    f12_a[m][k] = (A12_a F)[m][k], vec(f12_a)[m M_z + k] = f12_a[m][k],
+
+and the adjoint of the whole aperture is the transpose of the map from f to
+all columns' data: sum over a of (A12_a)^T unvec((A34)^T y_a). The products
+below are scipy sparse products; nothing is blocked or reordered beyond
+stacking the columns, so that a reader can check each line against these
+formulas. The GPU path (Alg. 1 and Alg. 2) is checked against it.
+
+Layouts: volume F[k][j][i] (z, y, x), pixel p = j M_s + i; data Y[a][h][l]
+(column, sensor height, sphere radius, radius fastest), row h N_l + l of A34.
 """
 from __future__ import annotations
 
 import numpy as np
+import scipy.sparse as sp
 
 
-def stage1(a12, F: np.ndarray) -> np.ndarray:
-    """Alg. 1, first product: reshape F to M_s^2 x M_z (pixel by slice) and
-    apply the circle transform in every slice: G = A12 F, N_rho x M_z."""
-    mz = F.shape[0]
-    F2 = F.reshape(mz, -1).T
-    return np.asarray(a12 @ F2)
+def pixels_by_slice(F: np.ndarray) -> np.ndarray:
+    """F[k][j][i] as the matrix F[p][k] (pixel p = j M_s + i, slice k)."""
+    return F.reshape(F.shape[0], -1).T
 
 
-def stage2(a34, G: np.ndarray, n_z: int, n_radii: int) -> np.ndarray:
-    """Alg. 1, second product: flatten G to a vector of length N_rho M_z,
-    apply the half-circle transform and reshape to N_h x N_l."""
-    return np.asarray(a34 @ G.reshape(-1)).reshape(n_z, n_radii)
+def crt12(a12, F: np.ndarray) -> np.ndarray:
+    """CRT12 of one column: its circle transform in every z-plane,
+    f12[m][k] = sum over p of A12[m, p] F[k, p] (N_rho x M_z)."""
+    return np.asarray(a12 @ pixels_by_slice(F))
 
 
-def column_srt(F: np.ndarray, a12, a34, n_z: int, n_radii: int) -> np.ndarray:
-    """Alg. 1 (ColumnSRT) for one sensor column."""
-    return stage2(a34, stage1(a12, F), n_z, n_radii)
+def crt34(a34, f12: np.ndarray, n_z: int, n_radii: int) -> np.ndarray:
+    """CRT34 of one column's image: the half-circle integrals of f12 about
+    every sensor, Y[h][l] = sum over (m, k) of A34[(h, l), (m, k)] f12[m][k]."""
+    return np.asarray(a34 @ f12.reshape(-1)).reshape(n_z, n_radii)
+
+
+def crt34_t(a34, y: np.ndarray, mz: int) -> np.ndarray:
+    """Transpose of crt34: f12'[m][k] = sum over (h, l) of A34[(h, l), (m, k)] y[h][l]."""
+    return np.asarray(a34.T @ y.reshape(-1)).reshape(-1, mz)
+
+
+def crt12_t(a12, f12p: np.ndarray, ms: int) -> np.ndarray:
+    """Transpose of crt12: F'[k][j][i] = sum over m of A12[m, p] f12'[m][k]."""
+    Fp = np.asarray(a12.T @ f12p)  # [p][k]
+    return Fp.T.reshape(f12p.shape[1], ms, ms)
 
 
 def forward(F: np.ndarray, a12s, a34, n_z: int, n_radii: int) -> np.ndarray:
-    """Alg. 1 over every column of the aperture: Y[a][h][l]."""
-    return np.stack([column_srt(F, a, a34, n_z, n_radii) for a in a12s])
-
-
-def adj_stage2(a34, Y_a: np.ndarray, mz: int) -> np.ndarray:
-    """Alg. 2, first product: G' = (A34)^T y, reshaped to N_rho x M_z (the
-    radial axis of the stage-2 image; N_rho = N_l unless it has its own)."""
-    return np.asarray(a34.T @ Y_a.reshape(-1)).reshape(-1, mz)
-
-
-def adj_stage1(a12, Gp: np.ndarray, ms: int) -> np.ndarray:
-    """Alg. 2, second product: F' = (A12)^T G', reshaped to M_z x M_s x M_s."""
-    Fp = np.asarray(a12.T @ Gp)  # [p][k]
-    return Fp.T.reshape(Gp.shape[1], ms, ms)
-
-
-def column_adjoint(Y_a: np.ndarray, a12, a34, ms: int, mz: int) -> np.ndarray:
-    """Alg. 2 (AdjColumnSRT) for one sensor column."""
-    return adj_stage1(a12, adj_stage2(a34, Y_a, mz), ms)
+    """SRT of every column of the aperture, Y[a][h][l] = SRT_a f: the
+    columns' circle transforms as one product with the stacked A12, then A34
+    applied to every column's image at once."""
+    na, mz = len(a12s), F.shape[0]
+    f12 = np.asarray(sp.vstack(a12s).tocsr() @ pixels_by_slice(F))  # [a N_rho + m][k]
+    images = f12.reshape(na, -1)  # row a: vec(f12_a)
+    Y = np.asarray(a34 @ images.T).T  # [a][h N_l + l]
+    return Y.reshape(na, n_z, n_radii)
 
 
 def adjoint(Y: np.ndarray, a12s, a34, ms: int, mz: int) -> np.ndarray:
-    """Alg. 2 summed over the columns of the aperture: F'[k][j][i]."""
-    out = np.zeros((mz, ms, ms))
-    for a, A in enumerate(a12s):
-        out += column_adjoint(Y[a], A, a34, ms, mz)
-    return out
+    """The transpose of forward: F'[k][j][i] = sum over a of
+    (A12_a)^T unvec((A34)^T y_a), as two products with the transposed
+    operators (the sum over columns is the product with the stacked A12)."""
+    na = len(a12s)
+    images = np.asarray(a34.T @ Y.reshape(na, -1).T).T  # row a: vec(f12'_a)
+    Fp = np.asarray(sp.vstack(a12s).tocsr().T @ images.reshape(-1, mz))  # [p][k]
+    return Fp.T.reshape(mz, ms, ms)
 
 
 def flops(a12s, a34, mz: int) -> int:

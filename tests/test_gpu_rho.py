@@ -138,7 +138,7 @@ def test_pact256_half_rho_grid_sampled():
     angles, heights = [0, 300], [0, 101, 255]
     a34 = geo.assemble_a34(ap, heights=heights)
     for a in angles:
-        G = osrt.stage1(geo.assemble_a12(ap, ap.angles[a]), Fin).reshape(-1)
+        G = osrt.crt12(geo.assemble_a12(ap, ap.angles[a]), Fin).reshape(-1)
         for h in heights:
             rows = a34[h * ap.n_radii:(h + 1) * ap.n_radii]
             assert rel_l2(Y[a, h], rows @ G) <= 1e-5, (a, h)

@@ -151,7 +151,7 @@ def _stage1_disk_error(m, nl):
     F = np.stack([frac, -2.0 * frac])
     errs = []
     for ang in ap.angles:
-        G = srt.stage1(geo.assemble_a12(ap, ang), F)
+        G = srt.crt12(geo.assemble_a12(ap, ang), F)
         d = np.hypot(ap.radius * np.cos(ang) - 0.2, ap.radius * np.sin(ang) + 0.1)
         ex = cf.circle_in_disk(ap.radii, d, 0.5)
         assert np.allclose(G[:, 1], -2.0 * G[:, 0], rtol=1e-14, atol=1e-14)
@@ -173,7 +173,7 @@ def _stage2_disk_error(m, nl):
     a34 = geo.assemble_a34(ap)
     G = _disk_fraction(geo.grid_edges(ap.z0, ap.dz, ap.mz), geo.rho_edges(ap.radii),
                        0.1, 1.0, 0.4)
-    Y = srt.stage2(a34, G, ap.n_z, ap.n_radii)
+    Y = srt.crt34(a34, G, ap.n_z, ap.n_radii)
     d = np.hypot(ap.zpos - 0.1, 1.0)
     ex = cf.circle_in_disk(ap.radii[None, :], d[:, None], 0.4)
     return np.linalg.norm(Y - ex) / np.linalg.norm(ex)
