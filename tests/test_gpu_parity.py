@@ -4,7 +4,8 @@ Tolerances (relative L2 over a whole output unless stated):
   FP64 values and weights   1e-12
   FP32 values and weights   1e-5
   BF16 / FP16 weights       5e-3
-  adjoint dot test (FP32)   1e-6 of ||A f|| ||g||
+  adjoint dot test          1e-6 of |<A f, g>| (the Cauchy-Schwarz form,
+                            |<Af,g> - <f,A^T g>| / (||A f|| ||g||), is printed beside it)
   operator entries (FP64)   1e-12 * pitch per entry
 """
 import numpy as np
@@ -39,6 +40,18 @@ def _t(x, dtype):
 
 def _np(t):
     return t.detach().to("cpu", torch.float64).numpy()
+
+
+def _dot(Y, g, F, Fg):
+    """Dot test on device results, inner products in FP64: the error
+    |<A f, g> - <f, A^T g>| relative to |<A f, g>| (asserted), and relative to
+    the Cauchy-Schwarz bound ||A f|| ||g|| (a weaker measure, printed)."""
+    lhs = float((Y.double() * g.double()).sum())
+    rhs = float((F.double() * Fg.double()).sum())
+    rel = abs(lhs - rhs) / abs(lhs)
+    cs = abs(lhs - rhs) / (float(Y.double().norm()) * float(g.double().norm()))
+    print(f"dot test: relative {rel:.2e}, Cauchy-Schwarz {cs:.2e}")
+    return rel
 
 
 # ------------------------------------------------------------------ operators
@@ -287,10 +300,9 @@ def test_grid128_forward_adjoint_f32(grid128):
     assert rel_l2(_np(Yg), Y) <= 1e-5
     Fg = plan.adjoint(gt)
     assert rel_l2(_np(Fg), Fp) <= 1e-5
-    # dot test on the device results, inner products in FP64
-    lhs = float((Yg.double() * gt.double()).sum())
-    rhs = float((Ft[None].double() * Fg.double()).sum())
-    assert abs(lhs - rhs) / (float(Yg.double().norm()) * float(gt.double().norm())) <= 1e-6
+    # dot tests: N(0,1) data, and its absolute value (no cancellation in <Af, g>)
+    assert _dot(Yg, gt, Ft[None], Fg) <= 1e-6
+    assert _dot(Yg, gt.abs(), Ft[None], plan.adjoint(gt.abs())) <= 1e-6
 
 
 @pytest.mark.parametrize("weight", ["bf16", "f16"])
@@ -301,45 +313,73 @@ def test_grid128_rounded_weights(grid128, weight):
     Fg = plan.adjoint(gt)
     assert rel_l2(_np(Yg), Y) <= 5e-3
     assert rel_l2(_np(Fg), Fp) <= 5e-3
-    lhs = float((Yg.double() * gt.double()).sum())
-    rhs = float((Ft[None].double() * Fg.double()).sum())
-    assert abs(lhs - rhs) / (float(Yg.double().norm()) * float(gt.double().norm())) <= 1e-6
+    # the same rounded weights on both sides: the dot test holds as in FP32
+    assert _dot(Yg, gt, Ft[None], Fg) <= 1e-6
+    assert _dot(Yg, gt.abs(), Ft[None], plan.adjoint(gt.abs())) <= 1e-6
 
 
 # ------------------------------------------------------------------ pact256 (full size)
-def test_pact256_sampled_forward_and_sparse_adjoint():
-    """At the 256^3 PACT-scale workload, in the launch configuration the
-    benchmark times: forward outputs of sampled (column, height) pairs against
-    the oracle, and the full adjoint volume of data that is non-zero on a few
-    columns and heights (the oracle needs only those rows)."""
+# 32 columns spread over the whole angle range, three heights
+PACT_COLS = list(range(5, 512, 16))
+PACT_HEIGHTS = [10, 128, 245]
+
+
+@pytest.fixture(scope="module")
+def pact256_oracle():
+    """The FP32-cast 256^3 phantom, the oracle's A12 of 32 columns and its
+    A34 rows of three heights, the forward planes of those (column, height)
+    pairs, and the adjoint of N(0,1) data on all of them."""
     ap = config("pact256")
-    F = phantoms.phantom(ap)
-    Ft = _t(F, torch.float32)
+    Ft = _t(phantoms.phantom(ap), torch.float32)
     Fin = _np(Ft)
-    plan = _plan(ap, "f32")
-    Y = _np(plan.forward(Ft))
-    angles, heights = [0, 77, 300, 511], [0, 101, 255]
-    a34 = geo.assemble_a34(ap, heights=heights)
-    for a in angles:
-        G = osrt.stage1(geo.assemble_a12(ap, ap.angles[a]), Fin).reshape(-1)
-        for h in heights:
-            rows = a34[h * ap.n_radii:(h + 1) * ap.n_radii]
-            assert rel_l2(Y[a, h], rows @ G) <= 1e-5, (a, h)
+    a34 = geo.assemble_a34(ap, heights=PACT_HEIGHTS)
+    a12 = {a: geo.assemble_a12(ap, ap.angles[a]) for a in PACT_COLS}
+    fwd = {}
+    for a in PACT_COLS:
+        G = osrt.crt12(a12[a], Fin).reshape(-1)
+        for h in PACT_HEIGHTS:
+            fwd[a, h] = a34[h * ap.n_radii:(h + 1) * ap.n_radii] @ G
     rng = np.random.default_rng(2003)
     data = np.zeros(ap.data_shape)
-    sel_a, sel_h = [5, 260], [10, 128]
-    for a in sel_a:
-        for h in sel_h:
+    for a in PACT_COLS:
+        for h in PACT_HEIGHTS:
             data[a, h] = rng.standard_normal(ap.n_radii)
     dt = _t(data, torch.float32)
-    Fp = _np(plan.adjoint(dt))
     din = _np(dt)
-    a34s = geo.assemble_a34(ap, heights=sel_h)
-    ref = np.zeros(ap.vol_shape)
-    for a in sel_a:
-        Gp = osrt.adj_stage2(a34s, din[a], ap.mz)
-        ref += osrt.adj_stage1(geo.assemble_a12(ap, ap.angles[a]), Gp, ap.ms)
-    assert rel_l2(Fp, ref) <= 1e-5
+    adj = np.zeros(ap.vol_shape)
+    for a in PACT_COLS:
+        adj += osrt.crt12_t(a12[a], osrt.crt34_t(a34, din[a], ap.mz), ap.ms)
+    return ap, Ft, fwd, dt, adj
+
+
+@pytest.mark.parametrize("weight,tol", [("f32", 1e-5), ("bf16", 5e-3)])
+def test_pact256_sampled_forward_and_adjoint(pact256_oracle, weight, tol):
+    """At the 256^3 PACT-scale workload, in the launch configuration the
+    benchmark times: the forward's [h][l] planes of 32 columns spread over
+    the angle range at three heights each (96 planes) against the oracle, and
+    the whole adjoint volume of data that is non-zero on those 96 planes
+    (the oracle needs only their rows)."""
+    ap, Ft, fwd, dt, adj = pact256_oracle
+    plan = _plan(ap, "f32", weight)
+    Y = _np(plan.forward(Ft))
+    for (a, h), ref in fwd.items():
+        assert rel_l2(Y[a, h], ref) <= tol, (a, h)
+    assert rel_l2(_np(plan.adjoint(dt)), adj) <= tol
+
+
+@pytest.mark.parametrize("weight", ["f32", "bf16"])
+def test_pact256_dot_test(weight):
+    """At 256^3, the device's forward and adjoint agree as a transpose pair:
+    <A f, g> = <f, A^T g> to 1e-6 of |<A f, g>| for the phantom f and N(0,1)
+    data g on every column, height and radius, and for |g|. Inner products
+    in FP64; no oracle."""
+    ap = config("pact256")
+    F = _t(phantoms.phantom(ap), torch.float32)
+    plan = _plan(ap, "f32", weight)
+    g = _t(np.random.default_rng(2013).standard_normal(ap.data_shape), torch.float32)
+    Y = plan.forward(F)
+    assert _dot(Y, g, F, plan.adjoint(g)) <= 1e-6
+    assert _dot(Y, g.abs(), F, plan.adjoint(g.abs())) <= 1e-6
 
 
 @pytest.mark.parametrize("weight", ["bf16", "f16"])
@@ -355,7 +395,7 @@ def test_pact256_sampled_forward_16bit_weights(weight):
     angles, heights = [3, 260], [17, 200]
     a34 = geo.assemble_a34(ap, heights=heights)
     for a in angles:
-        G = osrt.stage1(geo.assemble_a12(ap, ap.angles[a]), Fin).reshape(-1)
+        G = osrt.crt12(geo.assemble_a12(ap, ap.angles[a]), Fin).reshape(-1)
         for h in heights:
             rows = a34[h * ap.n_radii:(h + 1) * ap.n_radii]
             assert rel_l2(Y[a, h], rows @ G) <= 5e-3, (a, h)
@@ -421,7 +461,7 @@ def test_pact256_square_columns_sampled():
     a34 = geo.assemble_a34(ap, heights=heights)
     a12 = {a: geo.assemble_a12_at(ap, ap.column_centers[a]) for a in cols}
     for a in cols:
-        G = osrt.stage1(a12[a], Fin).reshape(-1)
+        G = osrt.crt12(a12[a], Fin).reshape(-1)
         for h in heights:
             rows = a34[h * ap.n_radii:(h + 1) * ap.n_radii]
             assert rel_l2(Y[a, h], rows @ G) <= 1e-5, (a, h)
@@ -435,7 +475,7 @@ def test_pact256_square_columns_sampled():
     din = _np(dt)
     ref = np.zeros(ap.vol_shape)
     for a in cols[:2]:
-        ref += osrt.adj_stage1(a12[a], osrt.adj_stage2(a34, din[a], ap.mz), ap.ms)
+        ref += osrt.crt12_t(a12[a], osrt.crt34_t(a34, din[a], ap.mz), ap.ms)
     assert rel_l2(Fp, ref) <= 1e-5
 
 
