@@ -12,10 +12,17 @@ Prints one JSON line on stdout. Besides throughput it reports:
                 HIP events recorded by the library on the apply stream, against
                 the FP32 vector-ALU peak (157.3 TFLOP/s; gfx950 issues unpacked
                 v_fmac_f32 at that rate, packed FP32 is disabled in this build);
-                `traffic` comes from the committed rocprofv3 counter summary
-                when it was taken on the current kernel source, else null
-  hbm           compulsory bytes of a step (operators once, inputs, outputs)
-                over the step time, against 8 TB/s
+                beside it the same launch's LDS read rate (LDS instructions per
+                launch from the committed rocprofv3 counter summary, each a
+                16-byte read by 64 lanes) against the LDS peak (256 B/clk/CU x
+                256 CUs x 2.4 GHz = 157.3 TB/s) and its HBM traffic (counter
+                bytes per launch) against 8 TB/s; `bound` names the resource
+                closest to its peak. Counter figures are used only when they
+                were taken on the current kernel source, else null
+  hbm           bytes of a step over the step time, against 8 TB/s, by two
+                definitions: compulsory (each operator once, the input, the
+                stage-1 result written and read back, the output; per
+                direction) and io (operators once, inputs and outputs only)
   cpu_baseline  the FP64 oracle timed on the host on a bounded sample of the
                 same workload and scaled to one pair: one core, and beside it
                 ("parallel") one process per host core, split by column
@@ -25,8 +32,9 @@ Prints one JSON line on stdout. Besides throughput it reports:
                 accumulation): rate and relative L2 distance from the FP32-weight
                 results (default run only)
   serving       p50/p99 latency and throughput of a mixed stream of forward
-                and adjoint requests on 64^3/128^3/192^3 grids at 1000 req/s,
-                FP32 and BF16 weights, with the device-bound capacity of each
+                and adjoint requests on 64^3/128^3/192^3 grids at 1000 req/s
+                (5000 requests), FP32 and BF16 weights, with the device-bound
+                capacity of each and the BF16/FP32 ratios of capacity and p99
                 (default run only; --no-serving skips it)
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--weights f32|bf16|f16]
@@ -57,6 +65,9 @@ sys.path.insert(0, ROOT)
 METRIC = "SRT fwd+adjoint pairs/s at 256^3, HBM GB/s % of peak; serving p50/p99 latency"
 PEAK_FP32_VALU_TFLOPS = 157.3  # MI355X FP32 vector: 256 CUs x 128 FMA/clk x 2 FLOP x 2.4 GHz
 PEAK_HBM_GBPS = 8000.0
+# LDS reads: 256 bytes per clock per CU on gfx950, 256 CUs at 2.4 GHz
+PEAK_LDS_TBPS = 256 * 256 * 2.4e9 / 1e12
+LDS_BYTES_PER_INST = 64 * 16  # the stage kernels' LDS instructions are ds_read_b128
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stage_kernels_pact256.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2402_15641_amd", "csrc", f)
                   for f in ("apply.hip", "srt_internal.h")]
@@ -73,24 +84,34 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(kernel: str, launches_per_pair: int):
-    """HBM bytes per launch of `kernel` from the committed counter summary,
-    if it was taken on the current kernel source."""
+def counter_record(kernel: str):
+    """Per-launch counter figures of `kernel` from the committed summary, if
+    they were taken on the current kernel source (else None)."""
     try:
         rec = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
     if rec.get("source_sha256") != kernel_source_hash():
         return None
-    k = rec.get("kernels", {}).get(kernel)
-    if not k:
-        return None
-    return k["fetch_bytes"] + k["write_bytes"]
+    return rec.get("kernels", {}).get(kernel)
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` (calibrated FETCH_SIZE + WRITE_SIZE)."""
+    k = counter_record(kernel)
+    return None if not k else k["fetch_bytes"] + k["write_bytes"]
+
+
+def measured_lds_bytes(kernel: str):
+    """LDS bytes read per launch of `kernel` (SQ_INSTS_LDS x 1 KiB)."""
+    k = counter_record(kernel)
+    return None if not k or "sq_insts_lds" not in k else k["sq_insts_lds"] * LDS_BYTES_PER_INST
 
 
 def _oracle_sample(ap, F64, cols, heights, barrier=None):
-    """Assembles the sample's operators, then times Alg. 1 and Alg. 2 of the
-    columns `cols` with stage 2 on `heights`: (stage-1 s, stage-2 s, assembly s)."""
+    """Assembles the sample's operators, then times the oracle's forward and
+    adjoint transforms (CRT12 and CRT34 and their transposes) of the columns
+    `cols` with CRT34 on `heights`: (CRT12 s, CRT34 s, assembly s)."""
     from oracle import geometry as geo, srt as osrt
     t0 = time.perf_counter()
     a34 = geo.assemble_a34(ap, heights=heights)
@@ -101,14 +122,14 @@ def _oracle_sample(ap, F64, cols, heights, barrier=None):
     t1 = t2 = 0.0
     for A in a12s:
         s = time.perf_counter()
-        G = osrt.stage1(A, F64)
+        G = osrt.crt12(A, F64)
         t1 += time.perf_counter() - s
         s = time.perf_counter()
-        Y = osrt.stage2(a34, G, ap.n_z, ap.n_radii)
-        Gp = osrt.adj_stage2(a34, Y, ap.mz)
+        Y = osrt.crt34(a34, G, ap.n_z, ap.n_radii)
+        Gp = osrt.crt34_t(a34, Y, ap.mz)
         t2 += time.perf_counter() - s
         s = time.perf_counter()
-        osrt.adj_stage1(A, Gp, ap.ms)
+        osrt.crt12_t(A, Gp, ap.ms)
         t1 += time.perf_counter() - s
     return t1, t2, t_asm
 
@@ -118,8 +139,8 @@ def _oracle_worker(ap, F64, cols, heights, barrier, queue):
 
 
 def cpu_baseline(ap, F64, n_cols=32, h_stride=8, max_procs=16):
-    """The oracle (FP64, scipy CSR) on a bounded sample: Alg. 1 and Alg. 2 for
-    n_cols evenly spaced columns, with the stage-2 operator restricted to
+    """The oracle (FP64, scipy CSR) on a bounded sample: forward and adjoint
+    for n_cols evenly spaced columns, with the stage-2 operator restricted to
     every h_stride-th sensor height; stage-1 time is scaled by the columns
     left out, stage-2 time also by the heights left out. Timed once on one
     core, then with one process per host core (at most max_procs), the
@@ -171,23 +192,30 @@ def cpu_baseline(ap, F64, n_cols=32, h_stride=8, max_procs=16):
                      "threads_env": threads_env}}
 
 
-def serving_leg(rate=1000.0, seconds=2.0):
+def serving_leg(rate=1000.0, requests=5000):
     """p50/p99 latency and throughput of the mixed serving stream at one
     arrival rate, FP32 and BF16 weights (the full rate sweep is
     paper_2402_15641_amd.serve_bench)."""
     from paper_2402_15641_amd.serve_bench import serving_mix
     t0 = time.perf_counter()
-    recs = serving_mix([rate], seconds=seconds, pool=2)
+    recs = serving_mix([rate], seconds=requests / rate, min_requests=requests, pool=2)
     out = {"workload": "grids 64^3/128^3/192^3 drawn uniformly, N x N x 4N apertures, 70% "
                        "forward / 30% adjoint, Poisson arrivals, batches of up to 8 on 4 "
                        "streams, admission by device-memory footprint (16 GiB)",
-           "rate_rps": rate, "requests": int(rate * seconds)}
+           "rate_rps": rate}
     for r in recs:
         w = out.setdefault(r["weights"], {})
         if "device_bound_capacity_rps" in r:
             w["capacity_rps"] = r["device_bound_capacity_rps"]
         else:
-            w.update({k: r[k] for k in ("p50_ms", "p99_ms", "mean_ms", "throughput_rps")})
+            w.update({k: r[k] for k in ("p50_ms", "p99_ms", "mean_ms", "throughput_rps",
+                                        "requests")})
+    # BF16 against FP32 weights: by device-bound capacity (throughput at a
+    # rate below capacity only follows the arrivals) and by p99 latency
+    if "f32" in out and "bf16" in out:
+        out["bf16_over_f32"] = {
+            "capacity": out["bf16"]["capacity_rps"] / out["f32"]["capacity_rps"],
+            "p99": out["bf16"]["p99_ms"] / out["f32"]["p99_ms"]}
     log(f"serving leg {time.perf_counter() - t0:.1f} s")
     return out
 
@@ -306,19 +334,38 @@ def main():
     dom = max(stages, key=lambda k: stages[k][0])
     dom_ms, dom_flop = stages[dom]
     achieved = dom_flop / (dom_ms * 1e-3) / 1e12
-    traffic = None if variant else measured_traffic(dom, 1)
+    counters_ok = not variant and args.weights == "f32"  # the summary's configuration
+    traffic = measured_traffic(dom) if counters_ok else None
+    lds_bytes = measured_lds_bytes(dom) if counters_ok else None
     # HBM bytes the counters saw per launch, over each stage kernel's time
     measured = {}
-    if not variant:
+    if counters_ok:
         for k, (k_ms, _) in stages.items():
-            b = measured_traffic(k, 1)
+            b = measured_traffic(k)
             if b is not None:
                 measured[k] = b / (k_ms * 1e-3) / 1e9
+    frac_alu = achieved / PEAK_FP32_VALU_TFLOPS
+    lds = None
+    if lds_bytes is not None:
+        lds_tbps = lds_bytes / (dom_ms * 1e-3) / 1e12
+        lds = {"achieved": lds_tbps, "peak": PEAK_LDS_TBPS, "unit": "TB/s",
+               "frac": lds_tbps / PEAK_LDS_TBPS, "bytes_per_launch": lds_bytes,
+               "bytes_per_fma": lds_bytes / (dom_flop / 2)}
+    fractions = {"alu": frac_alu}
+    if lds:
+        fractions["lds"] = lds["frac"]
+    if traffic is not None:
+        fractions["hbm"] = traffic / (dom_ms * 1e-3) / 1e9 / PEAK_HBM_GBPS
+    bound = max(fractions, key=fractions.get)
 
     wb = {"f32": 4, "bf16": 2, "f16": 2}[args.weights]
     op_bytes = 2 * (nnz12 + nnz34) * (4 + wb)  # operator and its transpose, once each
-    io_bytes = 2 * 4 * nb * (int(np.prod(ap.vol_shape)) + int(np.prod(ap.data_shape)))
-    hbm_gbps = (op_bytes + io_bytes) / (ms_per_step * 1e-3) / 1e9
+    vol_b = 4 * nb * int(np.prod(ap.vol_shape))
+    dat_b = 4 * nb * int(np.prod(ap.data_shape))
+    g_b = 4 * nb * ap.n_angles * info["live_radii"] * ap.mz  # stage-1 result (live rho cells)
+    io_bytes = op_bytes + 2 * (vol_b + dat_b)
+    comp_bytes = io_bytes + 2 * 2 * g_b  # plus G written and read back, each direction
+    step_s = ms_per_step * 1e-3
 
     result = {
         "metric": METRIC,
@@ -340,12 +387,16 @@ def main():
                    "batch": nb, "weights": args.weights, "phantom": "seeded",
                    "basis": args.basis, "n_rho": info["n_rho"], "aperture": args.aperture,
                    "nnz_a12": nnz12, "nnz_a34": nnz34, "plan_build_s": round(t_plan, 3)},
-        "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved,
+        "roofline": {"bound": bound, "kernel": dom, "achieved": achieved,
                      "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_VALU_TFLOPS, "traffic": traffic,
-                     "launch_ms": dom_ms, "flop_per_launch": dom_flop},
-        "hbm": {"compulsory_bytes_per_step": op_bytes + io_bytes, "achieved_gbps": hbm_gbps,
-                "peak_gbps": PEAK_HBM_GBPS, "frac": hbm_gbps / PEAK_HBM_GBPS,
+                     "frac": frac_alu, "traffic": traffic,
+                     "launch_ms": dom_ms, "flop_per_launch": dom_flop,
+                     "fractions": fractions, "lds": lds},
+        "hbm": {"compulsory_bytes_per_step": comp_bytes,
+                "achieved_gbps": comp_bytes / step_s / 1e9, "peak_gbps": PEAK_HBM_GBPS,
+                "frac": comp_bytes / step_s / 1e9 / PEAK_HBM_GBPS,
+                "io_bytes_per_step": io_bytes, "io_gbps": io_bytes / step_s / 1e9,
+                "io_frac": io_bytes / step_s / 1e9 / PEAK_HBM_GBPS,
                 "measured_stage_gbps": measured or None},
         "step_ms": {"mean": ms_per_step, "median": float(np.median(steps_ms)),
                     "min": float(np.min(steps_ms))},

@@ -141,6 +141,12 @@ class GpuExecutor:
     """Runs batches through the C ABI on a pool of HIP streams (all at the
     default priority). Inputs are stacked into one device buffer per batch,
     the apply is launched on the batch's stream, and an event marks its end.
+    A batch's stream first waits for the stream that was current when the
+    batch was launched, so payloads written there are complete before they
+    are read, and device payloads are marked as used on the batch's stream so
+    that their memory is not reused while it reads them. At most n_streams
+    batches can be in flight (the scheduler's max_inflight must not exceed
+    it).
 
     With keep_results a finished request carries its output as a device
     tensor (a view of the batch output); without it the output is released
@@ -151,6 +157,7 @@ class GpuExecutor:
         self.torch = torch
         self.plans = plans
         self.keep_results = keep_results
+        self.n_streams = int(n_streams)
         self.streams = [torch.cuda.Stream() for _ in range(n_streams)]
         self.free = list(range(n_streams))
         self.inflight: list = []
@@ -162,8 +169,14 @@ class GpuExecutor:
     def launch(self, b: Batch, now: float):
         torch = self.torch
         plan = self.plans[b.plan]
+        if not self.free:
+            raise RuntimeError("no free stream: more batches in flight than n_streams")
         si = self.free.pop()
         s = self.streams[si]
+        s.wait_stream(torch.cuda.current_stream())
+        for r in b.reqs:
+            if r.payload.is_cuda:
+                r.payload.record_stream(s)
         with torch.cuda.stream(s):
             x = torch.stack([r.payload.to("cuda", non_blocking=True) for r in b.reqs])
             # each batch gets its own workspace: batches of one plan may overlap
@@ -212,6 +225,8 @@ def serve(trace: List[Request], sched: Scheduler, ex, realtime: bool = True) -> 
     """Runs the arrival trace to completion. Requests become visible to the
     scheduler at their arrival time; batches launch as soon as admission
     allows and complete asynchronously."""
+    if sched.max_inflight > getattr(ex, "n_streams", sched.max_inflight):
+        raise ValueError("the scheduler's max_inflight exceeds the executor's streams")
     pending = sorted(trace, key=lambda r: r.arrival)
     i = 0
     n = len(pending)

@@ -24,7 +24,7 @@ import sys
 import numpy as np
 
 
-def serving_mix(rates, weights=("f32", "bf16"), seconds=10.0, max_requests=5000,
+def serving_mix(rates, weights=("f32", "bf16"), seconds=10.0, min_requests=5000,
                 budget_gib=16.0, sizes=(64, 128, 192), pool=16, log=None):
     """Runs the mixed request stream at each rate for each weight type and
     returns the records: per weight type one capacity record (device time
@@ -77,7 +77,7 @@ def serving_mix(rates, weights=("f32", "bf16"), seconds=10.0, max_requests=5000,
               "device_bound_capacity_rps": 1000.0 / mix_ms})
         for rate in rates:
             rng = np.random.default_rng(int(rate) + (0 if w == "f32" else 1))
-            nreq = int(min(max_requests, max(200, rate * seconds)))
+            nreq = int(max(min_requests, rate * seconds))
             t = np.cumsum(rng.exponential(1.0 / rate, nreq))
             reqs = []
             for i in range(nreq):
@@ -104,16 +104,16 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--rates", type=float, nargs="+", default=[50, 100, 200, 500, 1000, 2000, 5000, 10000])
     ap.add_argument("--weights", nargs="+", default=["f32", "bf16"])
-    ap.add_argument("--max-requests", type=int, default=5000)
+    ap.add_argument("--min-requests", type=int, default=5000)
     ap.add_argument("--seconds", type=float, default=10.0,
-                    help="trace length per rate is min(max_requests, rate * seconds)")
+                    help="trace length per rate is max(min_requests, rate * seconds)")
     ap.add_argument("--budget-gib", type=float, default=16.0)
     ap.add_argument("--sizes", type=int, nargs="+", default=[64, 128, 192])
     args = ap.parse_args()
 
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     sys.path.insert(0, root)
-    serving_mix(args.rates, args.weights, args.seconds, args.max_requests, args.budget_gib,
+    serving_mix(args.rates, args.weights, args.seconds, args.min_requests, args.budget_gib,
                 args.sizes, log=lambda rec: print(json.dumps(rec), flush=True))
 
 

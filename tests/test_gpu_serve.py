@@ -48,3 +48,46 @@ def test_results_alone_equal_results_in_the_mix():
         assert torch.equal(alone, r.result), r.rid
     st = latency_stats(done)
     assert st["n"] == 48 and st["p99_ms"] >= st["p50_ms"] > 0
+
+
+@pytest.mark.parametrize("weights", ["f32", "bf16"])
+def test_serving_mix_grids_alone_equal_mix(weights):
+    """The served workload itself: grids of 64^3, 128^3 and 192^3 (N columns x
+    N heights x 4N radii), FP32 or BF16 operator weights with FP32
+    accumulation, 96 mixed requests (70% forward, 30% adjoint) arriving
+    faster than they complete, so batches of different grids overlap on the
+    device. Every result equals the same request applied alone, bitwise."""
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm device")
+    from paper_2402_15641_amd import SRTPlan
+    from paper_2402_15641_amd.serve import (GpuExecutor, Request, Scheduler, latency_stats,
+                                            plan_footprint_fn, serve)
+    from srt_inputs import config
+    plans = {f"n{n}": SRTPlan.from_geometry(config(f"serve{n}"), value_dtype="f32",
+                                            weight_dtype=weights) for n in (64, 128, 192)}
+    rng = np.random.default_rng(15)
+    pools = {k: {"fwd": [torch.from_numpy(rng.standard_normal(p.vol_shape)).float().cuda()
+                         for _ in range(3)],
+                 "adj": [torch.from_numpy(rng.standard_normal(p.data_shape)).float().cuda()
+                         for _ in range(3)]} for k, p in plans.items()}
+    reqs, t = [], 0.0
+    for i in range(96):
+        key = sorted(plans)[rng.integers(3)]
+        kind = "fwd" if rng.random() < 0.7 else "adj"
+        t += rng.exponential(1.0 / 4000.0)
+        reqs.append(Request(i, key, kind, pools[key][kind][rng.integers(3)], t))
+    fp = plan_footprint_fn(plans)
+    budget = 2 * fp("n192", "fwd", 8)
+    sched = Scheduler(fp, budget, max_batch=8, max_inflight=4)
+    done = serve(reqs, sched, GpuExecutor(plans, n_streams=4))
+    torch.cuda.synchronize()
+    assert len(done) == 96 and not sched.rejected
+    assert sched.peak_in_use <= budget
+    for r in done:
+        p = plans[r.plan]
+        alone = p.forward(r.payload) if r.kind == "fwd" else p.adjoint(r.payload)
+        assert torch.equal(alone, r.result), (r.rid, r.plan, r.kind)
+    st = latency_stats(done)
+    print(f"{weights}: p50 {st['p50_ms']:.2f} ms, p99 {st['p99_ms']:.2f} ms")
+    for p in plans.values():
+        p.close()
