@@ -54,7 +54,7 @@ def crt34_t(a34, y: np.ndarray, mz: int) -> np.ndarray:
 def crt12_t(a12, f12p: np.ndarray, ms: int) -> np.ndarray:
     """Transpose of crt12: F'[k][j][i] = sum over m of A12[m, p] f12'[m][k]."""
     Fp = np.asarray(a12.T @ f12p)  # [p][k]
-    return Fp.T.reshape(f12p.shape[1], ms, ms)
+    return np.ascontiguousarray(Fp.T).reshape(f12p.shape[1], ms, ms)
 
 
 def forward(F: np.ndarray, a12s, a34, n_z: int, n_radii: int) -> np.ndarray:
@@ -64,7 +64,7 @@ def forward(F: np.ndarray, a12s, a34, n_z: int, n_radii: int) -> np.ndarray:
     na, mz = len(a12s), F.shape[0]
     f12 = np.asarray(sp.vstack(a12s).tocsr() @ pixels_by_slice(F))  # [a N_rho + m][k]
     images = f12.reshape(na, -1)  # row a: vec(f12_a)
-    Y = np.asarray(a34 @ images.T).T  # [a][h N_l + l]
+    Y = np.ascontiguousarray(np.asarray(a34 @ images.T).T)  # [a][h N_l + l]
     return Y.reshape(na, n_z, n_radii)
 
 
@@ -75,7 +75,7 @@ def adjoint(Y: np.ndarray, a12s, a34, ms: int, mz: int) -> np.ndarray:
     na = len(a12s)
     images = np.asarray(a34.T @ Y.reshape(na, -1).T).T  # row a: vec(f12'_a)
     Fp = np.asarray(sp.vstack(a12s).tocsr().T @ images.reshape(-1, mz))  # [p][k]
-    return Fp.T.reshape(mz, ms, ms)
+    return np.ascontiguousarray(Fp.T).reshape(mz, ms, ms)
 
 
 def flops(a12s, a34, mz: int) -> int:

@@ -286,6 +286,8 @@ def test_dot_product(grid32):
     Fp = srt.adjoint(g, a12s, a34, ap.ms, ap.mz)
     rel = abs((Y * g).sum() - (F * Fp).sum()) / (np.linalg.norm(Y) * np.linalg.norm(g))
     assert rel <= 1e-13
+    # results in C order, as the device layouts expect them
+    assert Y.flags.c_contiguous and Fp.flags.c_contiguous
 
 
 def test_adjoint_is_explicit_transpose(grid32):
