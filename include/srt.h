@@ -225,6 +225,26 @@ srt_status srt_forward(srt_plan *plan, const void *vol, void *data, int32_t batc
 srt_status srt_adjoint(srt_plan *plan, const void *data, void *vol, int32_t batch,
                        void *workspace, size_t workspace_bytes, void *hip_stream);
 
+/*
+ * srt_forward_noalloc -- srt_forward (Alg. 1) for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc. It takes no workspace argument and calls
+ * no allocating routine; its workspace is a fixed 256 MiB array inside the
+ * library, one per device, which that device holds until the process ends.
+ *   plan, vol, data, batch, hip_stream  as in srt_forward
+ * Same kernels, same results (bitwise) as srt_forward. Every call on one
+ * device shares that device's array: calls that overlap on one device (other
+ * streams, other threads, other plans) race and must be serialised by the
+ * caller. Nothing in the array has to start at zero; each call overwrites
+ * what it reads. Stage timing (srt_plan_set_timing) does not record these
+ * calls.
+ * Errors: EINVAL (as srt_forward, and when the workspace srt_plan_footprint
+ * reports for this batch exceeds 256 MiB), ENOTSUP (device ordinal >= 64),
+ * EDEVICE.
+ */
+srt_status srt_forward_noalloc(srt_plan *plan, const void *vol, void *data, int32_t batch,
+                               void *hip_stream);
+
 /* Releases the plan's device memory. NULL is accepted. Work queued on the
  * plan must have completed (synchronise its streams first). */
 srt_status srt_plan_destroy(srt_plan *plan);

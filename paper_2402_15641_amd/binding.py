@@ -22,7 +22,7 @@ MODES = {"auto": 0, "stored": 1, "onthefly": 2}
 BASES = {"constant": 0, "linear": 1}
 
 # Every entry point declared in include/srt.h.
-SYMBOLS = ("srt_plan_create", "srt_plan_create_columns", "srt_plan_create_desc", "srt_forward", "srt_adjoint", "srt_plan_destroy",
+SYMBOLS = ("srt_plan_create", "srt_plan_create_columns", "srt_plan_create_desc", "srt_forward", "srt_adjoint", "srt_forward_noalloc", "srt_plan_destroy",
            "srt_plan_footprint", "srt_plan_get_info", "srt_plan_export_coo",
            "srt_plan_set_timing", "srt_plan_stage_times", "srt_cgls", "srt_cgls_workspace",
            "srt_nnls", "srt_nnls_workspace", "srt_opnorm2", "srt_last_error")
@@ -80,6 +80,7 @@ def lib() -> ctypes.CDLL:
     L.srt_plan_create_desc.argtypes = [ctypes.POINTER(SrtPlanDesc), P, ctypes.POINTER(P)]
     L.srt_forward.argtypes = [P, P, P, I32, P, SZ, P]
     L.srt_adjoint.argtypes = [P, P, P, I32, P, SZ, P]
+    L.srt_forward_noalloc.argtypes = [P, P, P, I32, P]
     L.srt_plan_destroy.argtypes = [P]
     L.srt_plan_footprint.argtypes = [P, I32, ctypes.POINTER(SZ), ctypes.POINTER(SZ)]
     L.srt_plan_get_info.argtypes = [P, ctypes.POINTER(SrtPlanInfo)]
@@ -208,6 +209,12 @@ def srt_adjoint(plan: int, data, vol, batch: int, workspace=None, stream=None) -
                                                               workspace.numel() * workspace.element_size())
     _check(lib().srt_adjoint(plan, data.data_ptr(), vol.data_ptr(), int(batch), ws_ptr, ws_bytes,
                              _stream_ptr(stream)), "srt_adjoint")
+
+
+def srt_forward_noalloc(plan: int, vol, data, batch: int, stream=None) -> None:
+    """srt_forward over the library's own fixed scratch array (no allocation)."""
+    _check(lib().srt_forward_noalloc(plan, vol.data_ptr(), data.data_ptr(), int(batch),
+                                     _stream_ptr(stream)), "srt_forward_noalloc")
 
 
 def srt_plan_footprint(plan: int, batch: int):

@@ -18,6 +18,8 @@
 //   data [b][a][h][l]     caller layout
 // L = live rho cells (circles of larger radius miss the grid).
 #include <algorithm>
+#include <mutex>
+#include <string>
 #include <type_traits>
 
 #include "srt_internal.h"
@@ -750,8 +752,8 @@ Status get_workspace(srt_plan *p, int32_t B, void *ws, size_t ws_bytes, hipStrea
   return Status{};
 }
 
-Status apply(srt_plan *p, const void *in, void *out, int32_t B, void *ws, size_t ws_bytes,
-             hipStream_t s, bool adjoint) {
+// Checks shared by every apply entry point.
+Status check_apply(const srt_plan *p, const void *in, const void *out, int32_t B) {
   if (!p || p->magic != kPlanMagic) return fail(SRT_EINVAL, "plan is NULL or not a live plan");
   if (!in || !out) return fail(SRT_EINVAL, "NULL input or output");
   if (B <= 0) return fail(SRT_EINVAL, "batch must be >= 1");
@@ -761,29 +763,15 @@ Status apply(srt_plan *p, const void *in, void *out, int32_t B, void *ws, size_t
   const size_t esz = dtype_size(p->vdtype);
   if (reinterpret_cast<uintptr_t>(in) % esz != 0 || reinterpret_cast<uintptr_t>(out) % esz != 0)
     return fail(SRT_EINVAL, "input and output must be aligned to their element size");
-  if (ws && reinterpret_cast<uintptr_t>(ws) % 16 != 0)
-    return fail(SRT_EINVAL, "workspace must be 16-byte aligned");
   const Geometry &g = p->geo;
   if ((int64_t)B * g.mz > INT32_MAX / 4 || (int64_t)B * g.na > INT32_MAX / 4)
     return fail(SRT_ENOTSUP, "batch too large");
-  DeviceScope ds(p->device);
-  if (ds.err != hipSuccess) return hip_fail(ds.err, "hipSetDevice");
-  void *P = nullptr, *Q = nullptr;
-  SRT_TRY(get_workspace(p, B, ws, ws_bytes, s, &P, &Q));
-  Marks mk;
-  mk.s = s;
-  if (p->timing) {
-    StageEvents rec;
-    for (int i = 0; i <= kStages; ++i) {
-      hipError_t e = hipEventCreate(&rec.ev[i]);
-      if (e != hipSuccess) {
-        for (int j = 0; j < i; ++j) (void)hipEventDestroy(rec.ev[j]);
-        return hip_fail(e, "hipEventCreate");
-      }
-    }
-    p->timed[adjoint ? 1 : 0].push_back(rec);
-    mk.rec = &p->timed[adjoint ? 1 : 0].back();
-  }
+  return Status{};
+}
+
+// The value/weight type dispatch of one apply over workspace buffers P, Q.
+Status run(srt_plan *p, const void *in, void *out, int32_t B, void *P, void *Q, hipStream_t s,
+           const Marks &mk, bool adjoint) {
   if (p->vdtype == SRT_F64) {
     using T = double;
     return adjoint ? adjoint_impl<T, double>(p, (const T *)in, (T *)out, B, (T *)P, (T *)Q, s, mk)
@@ -803,6 +791,77 @@ Status apply(srt_plan *p, const void *in, void *out, int32_t B, void *ws, size_t
       return adjoint ? adjoint_impl<T, float>(p, (const T *)in, (T *)out, B, (T *)P, (T *)Q, s, mk)
                      : forward_impl<T, float>(p, (const T *)in, (T *)out, B, (T *)P, (T *)Q, s, mk);
   }
+}
+
+Status apply(srt_plan *p, const void *in, void *out, int32_t B, void *ws, size_t ws_bytes,
+             hipStream_t s, bool adjoint) {
+  SRT_TRY(check_apply(p, in, out, B));
+  if (ws && reinterpret_cast<uintptr_t>(ws) % 16 != 0)
+    return fail(SRT_EINVAL, "workspace must be 16-byte aligned");
+  DeviceScope ds(p->device);
+  if (ds.err != hipSuccess) return hip_fail(ds.err, "hipSetDevice");
+  void *P = nullptr, *Q = nullptr;
+  SRT_TRY(get_workspace(p, B, ws, ws_bytes, s, &P, &Q));
+  Marks mk;
+  mk.s = s;
+  if (p->timing) {
+    StageEvents rec;
+    for (int i = 0; i <= kStages; ++i) {
+      hipError_t e = hipEventCreate(&rec.ev[i]);
+      if (e != hipSuccess) {
+        for (int j = 0; j < i; ++j) (void)hipEventDestroy(rec.ev[j]);
+        return hip_fail(e, "hipEventCreate");
+      }
+    }
+    p->timed[adjoint ? 1 : 0].push_back(rec);
+    mk.rec = &p->timed[adjoint ? 1 : 0].back();
+  }
+  return run(p, in, out, B, P, Q, s, mk, adjoint);
+}
+
+// ---- the allocation-free forward (srt_forward_noalloc)
+// Its workspace is this file-scope array: every device the library runs on
+// holds one copy of it, at its own address, until the process ends. In host
+// code `scratch` names a host-side stand-in, not device memory; the device
+// address comes from hipGetSymbolAddress, once per device, and only that
+// address is passed to kernels.
+constexpr size_t kScratchBytes = (size_t)256 << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+
+// Device address of `scratch` on the current device `dev`, looked up on the
+// first call for that device.
+Status scratch_address(int dev, void **out) {
+  static std::mutex mu;
+  static void *addr[kMaxDevices] = {};
+  if (dev < 0 || dev >= kMaxDevices) return fail(SRT_ENOTSUP, "device ordinal beyond the scratch table");
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void *a = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&a, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!a) return fail(SRT_EDEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+    addr[dev] = a;
+  }
+  *out = addr[dev];
+  return Status{};
+}
+
+Status forward_noalloc(srt_plan *p, const void *vol, void *data, int32_t B, hipStream_t s) {
+  SRT_TRY(check_apply(p, vol, data, B));
+  const size_t need = workspace_bytes(p, B);
+  if (need > kScratchBytes)
+    return fail(SRT_EINVAL, "srt_forward_noalloc: this plan and batch need " + std::to_string(need) +
+                                " bytes of workspace, more than its " +
+                                std::to_string(kScratchBytes) + "-byte scratch array");
+  DeviceScope ds(p->device);
+  if (ds.err != hipSuccess) return hip_fail(ds.err, "hipSetDevice");
+  void *base = nullptr;
+  SRT_TRY(scratch_address(p->device, &base));
+  const size_t one = need / 2;  // two equal, 256-byte aligned buffers
+  Marks mk;  // no stage timing: recording it would allocate events
+  mk.s = s;
+  return run(p, vol, data, B, base, (char *)base + one, s, mk, false);
 }
 
 }  // namespace
@@ -832,6 +891,15 @@ srt_status srt_adjoint(srt_plan *plan, const void *data, void *vol, int32_t batc
   return srt::apply(plan, data, vol, batch, workspace, workspace_bytes, (hipStream_t)hip_stream,
                     true)
       .code;
+}
+
+srt_status srt_forward_noalloc(srt_plan *plan, const void *vol, void *data, int32_t batch,
+                               void *hip_stream) {
+  try {
+    return srt::forward_noalloc(plan, vol, data, batch, (hipStream_t)hip_stream).code;
+  } catch (...) {
+    return srt::fail(SRT_ENOMEM, "host exception in srt_forward_noalloc").code;
+  }
 }
 
 }  // extern "C"

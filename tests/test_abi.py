@@ -73,6 +73,7 @@ def test_null_plan_calls():
     assert L.srt_plan_destroy(None) == B.SRT_OK
     assert L.srt_forward(None, None, None, 1, None, 0, None) == B.SRT_EINVAL
     assert L.srt_adjoint(None, None, None, 1, None, 0, None) == B.SRT_EINVAL
+    assert L.srt_forward_noalloc(None, None, None, 1, None) == B.SRT_EINVAL
     r = ctypes.c_size_t()
     assert L.srt_plan_footprint(None, 1, ctypes.byref(r), None) == B.SRT_EINVAL
     n = ctypes.c_int64()
