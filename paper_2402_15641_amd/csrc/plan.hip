@@ -178,14 +178,30 @@ Status create(const srt_grid *grid, int32_t basis, const double *col_xy, int32_t
   // y-neighbouring pixels (A12^T). Shapes, slot order and block numbering
   // tiles (2 column groups for A12, 2 height groups for A34, 4 rho groups
   // for A34^T, plain row-major for A12^T) were measured at 256^3 under the
-  // kernels' work order.
+  // kernels' work order. The forward operators cut their blocks' columns into
+  // chunks in polar order about the block (sectors of the block's arcs).
   const int64_t L = p->live;
   const int me = vdt == SRT_F64 ? kE64 : kE32;
   const int64_t bh = kRB / 16;  // 16 or 8
-  if (st.ok()) st = build_tiled(p->a12, RowGrid{na, L, 8, kRB / 8, true, 2}, me, s, &p->t12);
-  if (st.ok()) st = build_tiled(p->a12t, RowGrid{grid->ms, grid->ms, bh, 16, true, 1}, me, s, &p->t12t);
-  if (st.ok()) st = build_tiled(p->a34, RowGrid{nh, nl, 16, bh, true, 2}, me, s, &p->t34);
-  if (st.ok()) st = build_tiled(p->a34t, RowGrid{L, grid->mz, 16, bh, true, 4}, me, s, &p->t34t);
+  ColumnOrder o12, o34, plain;
+  o12.kind = 1;
+  o12.cx = g.cx;
+  o12.cy = g.cy;
+  o12.ms = g.ms;
+  o12.x0 = g.x0;
+  o12.dxy = g.dxy;
+  o34.kind = 2;
+  o34.zpos = g.zpos;
+  o34.rho = g.rho;
+  o34.mz = g.mz;
+  o34.z0 = g.z0;
+  o34.dz = g.dz;
+  if (st.ok()) st = build_tiled(p->a12, RowGrid{na, L, 8, kRB / 8, true, 2}, me, o12, s, &p->t12);
+  if (st.ok())
+    st = build_tiled(p->a12t, RowGrid{grid->ms, grid->ms, bh, 16, true, 1}, me, plain, s, &p->t12t);
+  if (st.ok()) st = build_tiled(p->a34, RowGrid{nh, nl, 16, bh, true, 2}, me, o34, s, &p->t34);
+  if (st.ok())
+    st = build_tiled(p->a34t, RowGrid{L, grid->mz, 16, bh, true, 4}, me, plain, s, &p->t34t);
   if (!st.ok()) return bail(st);
   p->magic = kPlanMagic;
   *out = p;

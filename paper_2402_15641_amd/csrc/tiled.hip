@@ -55,6 +55,16 @@ __device__ __forceinline__ void block_of(const RowGrid &g, int64_t row, int64_t 
   *slot = g.along_i1 ? (int)((i2 % g.b2) * g.b1 + i1 % g.b1) : (int)((i1 % g.b1) * g.b2 + i2 % g.b2);
 }
 
+// Inverse of block_of's numbering: the (i1 group, i2 group) of block blk.
+__device__ __forceinline__ void block_groups(const RowGrid &g, int64_t blk, int64_t *q1,
+                                             int64_t *q2) {
+  const int64_t nb1 = (g.n1 + g.b1 - 1) / g.b1, nb2 = (g.n2 + g.b2 - 1) / g.b2;
+  const int64_t t = blk / (g.tile * nb2), rem = blk - t * g.tile * nb2;
+  const int64_t w = nb1 - t * g.tile < g.tile ? nb1 - t * g.tile : g.tile;
+  *q2 = rem / w;
+  *q1 = t * g.tile + rem % w;
+}
+
 __device__ int64_t lower_bound_u64(const uint64_t *a, int64_t n, uint64_t v) {
   int64_t lo = 0, hi = n;
   while (lo < hi) {
@@ -100,6 +110,40 @@ __global__ void k_sorted_slots(const int32_t *__restrict__ idx_sorted,
   slot_sorted[i] = (uint8_t)slot;
 }
 
+// Sort key of distinct (block, column) key j under a polar column order:
+// block in the high word, the column's angle about the block's centre,
+// scaled to [0, 2^32), in the low word.
+__global__ void k_polar_keys(const uint64_t *__restrict__ ukeys, int64_t nu, RowGrid g,
+                             ColumnOrder o, uint64_t *__restrict__ okeys,
+                             int32_t *__restrict__ oidx) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nu) return;
+  const int64_t b = (int64_t)(ukeys[j] >> 32);
+  const int64_t col = (int64_t)(ukeys[j] & 0xffffffffu);
+  int64_t q1, q2;
+  block_groups(g, b, &q1, &q2);
+  const int64_t r0 = q1 * g.b1, r1 = r0 + g.b1 < g.n1 ? r0 + g.b1 : g.n1;
+  double px, py, cx = 0.0, cy = 0.0;
+  if (o.kind == 1) {  // pixel about the mean position of the block's sensor columns
+    for (int64_t r = r0; r < r1; ++r) {
+      cx += o.cx[r];
+      cy += o.cy[r];
+    }
+    px = o.x0 + ((double)(col % o.ms) + 0.5) * o.dxy;
+    py = o.x0 + ((double)(col / o.ms) + 0.5) * o.dxy;
+  } else {  // (rho, z) cell about the block's mean sensor height on the axis
+    for (int64_t r = r0; r < r1; ++r) cy += o.zpos[r];
+    px = o.rho[col / o.mz];
+    py = o.z0 + ((double)(col % o.mz) + 0.5) * o.dz;
+  }
+  const double n = (double)(r1 - r0);
+  const double a = atan2(py - cy / n, px - cx / n);  // (-pi, pi]
+  double u = (a + M_PI) / (2.0 * M_PI);
+  u = u < 0.0 ? 0.0 : (u >= 1.0 ? 0.0 : u);
+  okeys[j] = ((uint64_t)b << 32) | (uint64_t)(u * 4294967296.0);
+  oidx[j] = (int32_t)j;
+}
+
 // ustart[b]: first distinct (block, col) key of block b, b in [0, nblk].
 __global__ void k_ustart(const uint64_t *__restrict__ ukeys, int64_t nu, int64_t nblk,
                          int64_t *__restrict__ ustart) {
@@ -108,7 +152,7 @@ __global__ void k_ustart(const uint64_t *__restrict__ ukeys, int64_t nu, int64_t
   ustart[b] = lower_bound_u64(ukeys, nu, (uint64_t)b << 32);
 }
 
-// Greedy cut of each block's distinct columns (ascending) into chunks with at
+// Greedy cut of each block's distinct columns (in chunking order) into chunks with at
 // most kC columns and at most max_ent entries once every quad's rows are
 // padded to the quad's longest segment. One wavefront per block: lane l holds
 // the open chunk's entry counts of slots l*SPL .. l*SPL+SPL-1 in registers; the
@@ -122,9 +166,9 @@ static_assert(kRB % kChunkThreads == 0 && (kSPL == 2 || kSPL == 4) && kQ == 4,
               "a quad spans two lanes (two slots each) or one lane (four slots)");
 __global__ __launch_bounds__(kChunkThreads) void k_chunking(
     const int64_t *__restrict__ ustart, const int32_t *__restrict__ ucount,
-    const int64_t *__restrict__ upos, const uint8_t *__restrict__ slot_sorted, int64_t nblk,
-    int max_ent, int32_t *__restrict__ uchunk, int32_t *__restrict__ ulocal,
-    int64_t *__restrict__ nch) {
+    const int64_t *__restrict__ upos, const uint8_t *__restrict__ slot_sorted,
+    const int32_t *__restrict__ uorder, int64_t nblk, int max_ent,
+    int32_t *__restrict__ uchunk, int32_t *__restrict__ ulocal, int64_t *__restrict__ nch) {
   const int64_t b = blockIdx.x;
   const int lane = threadIdx.x;
   if (b == nblk) {
@@ -139,7 +183,10 @@ __global__ __launch_bounds__(kChunkThreads) void k_chunking(
   const bool quad_lead = kSPL == 4 || (lane & 1) == 0;
   int32_t chunk = 0, ncol = 0, padded = 0;
   const int64_t j0 = ustart[b], j1 = ustart[b + 1];
-  for (int64_t j = j0; j < j1; ++j) {
+  for (int64_t jj = j0; jj < j1; ++jj) {
+    // the block's distinct columns in chunking order (a permutation within
+    // the block's range)
+    const int64_t j = uorder ? uorder[jj] : jj;
     const int64_t e0 = upos[j];
     const int n = ucount[j];
     for (;;) {
@@ -336,7 +383,8 @@ void Tiled::release() {
   *this = Tiled{};
 }
 
-Status build_tiled(const Csr &m, const RowGrid &g, int max_ent, hipStream_t s, Tiled *out) {
+Status build_tiled(const Csr &m, const RowGrid &g, int max_ent, const ColumnOrder &order,
+                   hipStream_t s, Tiled *out) {
   if (g.n1 * g.n2 != m.nrows || g.b1 * g.b2 != kRB || max_ent < kRB)
     return fail(SRT_EDEVICE, "row grid does not match the operator");
   const int64_t nnz = m.nnz, nrows = m.nrows;
@@ -393,13 +441,32 @@ Status build_tiled(const Csr &m, const RowGrid &g, int max_ent, hipStream_t s, T
                        slot_sorted.as<uint8_t>());
     SRT_TRY(scan_to_i64(ucount.as<int32_t>(), upos.as<int64_t>(), nu, s, oom));
   }
-  // 2. chunks
+  // 2. chunks, cut along each block's columns in the requested order
   hipLaunchKernelGGL(k_ustart, dim3(nblocks(nblk + 1, t)), dim3(t), 0, s, ukeys.as<uint64_t>(), nu,
                      nblk, ustart.as<int64_t>());
+  Buf okeys, okeys_sorted, oidx, uorder;
+  if (order.kind != 0 && nu > 0) {
+    if (okeys.alloc(8 * nu) || okeys_sorted.alloc(8 * nu) || oidx.alloc(4 * nu) ||
+        uorder.alloc(4 * nu))
+      return oom();
+    hipLaunchKernelGGL(k_polar_keys, dim3(nblocks(nu, t)), dim3(t), 0, s, ukeys.as<uint64_t>(), nu,
+                       g, order, okeys.as<uint64_t>(), oidx.as<int32_t>());
+    // stable: columns at equal angles keep their index order
+    const int kbits = 32 + bits_for((uint64_t)nblk);
+    size_t b = 0;
+    Buf tmpo;
+    SRT_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, b, okeys.as<uint64_t>(),
+                                               okeys_sorted.as<uint64_t>(), oidx.as<int32_t>(),
+                                               uorder.as<int32_t>(), (int)nu, 0, kbits, s));
+    if (tmpo.alloc(b)) return oom();
+    SRT_HIP(hipcub::DeviceRadixSort::SortPairs(tmpo.p, b, okeys.as<uint64_t>(),
+                                               okeys_sorted.as<uint64_t>(), oidx.as<int32_t>(),
+                                               uorder.as<int32_t>(), (int)nu, 0, kbits, s));
+  }
   hipLaunchKernelGGL(k_chunking, dim3((unsigned)(nblk + 1)), dim3(kChunkThreads), 0, s,
                      ustart.as<int64_t>(), ucount.as<int32_t>(), upos.as<int64_t>(),
-                     slot_sorted.as<uint8_t>(), nblk, max_ent, uchunk.as<int32_t>(),
-                     ulocal.as<int32_t>(), nch.as<int64_t>());
+                     slot_sorted.as<uint8_t>(), order.kind != 0 ? uorder.as<int32_t>() : nullptr,
+                     nblk, max_ent, uchunk.as<int32_t>(), ulocal.as<int32_t>(), nch.as<int64_t>());
   SRT_TRY(scan_to_i64(nch.as<int64_t>(), chunk0.as<int64_t>(), nblk + 1, s, oom));
   int64_t nchunk = 0;
   SRT_HIP(hipMemcpyAsync(&nchunk, chunk0.as<int64_t>() + nblk, 8, hipMemcpyDeviceToHost, s));
