@@ -296,17 +296,19 @@ __device__ __forceinline__ void tiled_body(const int32_t *__restrict__ blk_rows,
     const uint32_t *wsrc = PACKED ? reinterpret_cast<const uint32_t *>(ent_w) + ce0
                                   : reinterpret_cast<const uint32_t *>(ent_w + ce0);
     if constexpr (BUF) {
+      // entry words in 16-byte pieces: a chunk holds whole quads (ne and nw
+      // are multiples of 4 words) and starts on a 16-byte boundary
       if constexpr (!PACKED) {
         const auto rc = buf_rsrc(ent_col + ce0, (uint32_t)ne * 4u);
-        for (int j = wave; j * 64 < ne; j += kNW) {
+        for (int j = wave; j * 256 < ne; j += kNW) {
           const int i = j * 64 + lane;
-          if (i < ne) buf_dma4(rc, (uint32_t)i * 4u, b.col + j * 64);
+          if (4 * i < ne) buf_dma16(rc, (uint32_t)i * 16u, b.col + j * 256);
         }
       }
       const auto rw = buf_rsrc(wsrc, (uint32_t)nw * 4u);
-      for (int j = wave; j * 64 < nw; j += kNW) {
+      for (int j = wave; j * 256 < nw; j += kNW) {
         const int i = j * 64 + lane;
-        if (i < nw) buf_dma4(rw, (uint32_t)i * 4u, b.w + j * 64);
+        if (4 * i < nw) buf_dma16(rw, (uint32_t)i * 16u, b.w + j * 256);
       }
     } else {
       if constexpr (!PACKED) {
