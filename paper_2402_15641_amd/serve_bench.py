@@ -24,7 +24,7 @@ import sys
 import numpy as np
 
 
-def serving_mix(rates, weights=("f32", "bf16"), seconds=10.0, min_requests=5000,
+def serving_mix(rates, weights=("f32", "bf16"), seconds=1.0, min_requests=5000,
                 budget_gib=16.0, sizes=(64, 128, 192), pool=16, log=None):
     """Runs the mixed request stream at each rate for each weight type and
     returns the records: per weight type one capacity record (device time
@@ -105,7 +105,7 @@ def main():
     ap.add_argument("--rates", type=float, nargs="+", default=[50, 100, 200, 500, 1000, 2000, 5000, 10000])
     ap.add_argument("--weights", nargs="+", default=["f32", "bf16"])
     ap.add_argument("--min-requests", type=int, default=5000)
-    ap.add_argument("--seconds", type=float, default=10.0,
+    ap.add_argument("--seconds", type=float, default=1.0,
                     help="trace length per rate is max(min_requests, rate * seconds)")
     ap.add_argument("--budget-gib", type=float, default=16.0)
     ap.add_argument("--sizes", type=int, nargs="+", default=[64, 128, 192])
