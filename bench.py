@@ -11,7 +11,7 @@ Prints one JSON line on stdout. Besides throughput it reports:
   roofline      the dominant kernel's algorithmic FLOP rate, timed live with
                 HIP events recorded by the library on the apply stream, against
                 the FP32 vector-ALU peak (157.3 TFLOP/s; gfx950 issues unpacked
-                v_fmac_f32 at that rate, packed FP32 is disabled in this build);
+                v_fmac_f32 at that rate; the library is compiled without packed FP32);
                 beside it the same launch's LDS read rate (LDS instructions per
                 launch from the committed rocprofv3 counter summary, each a
                 16-byte read by 64 lanes) against the LDS peak (256 B/clk/CU x

@@ -52,7 +52,7 @@ typedef enum {
                       workspace too small, destroyed plan */
   SRT_ENOMEM = 2,  /* device allocation failed or budget exceeded */
   SRT_EDEVICE = 3, /* a HIP runtime call failed */
-  SRT_ENOTSUP = 4  /* valid request this build does not implement */
+  SRT_ENOTSUP = 4  /* valid request the library does not implement */
 } srt_status;
 
 typedef enum { SRT_F32 = 0, SRT_F64 = 1, SRT_BF16 = 2, SRT_F16 = 3 } srt_dtype;
