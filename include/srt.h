@@ -57,9 +57,15 @@ typedef enum {
 
 typedef enum { SRT_F32 = 0, SRT_F64 = 1, SRT_BF16 = 2, SRT_F16 = 3 } srt_dtype;
 
-/* How the operators are held: STORED keeps CSR matrices and their
- * transposes resident in HBM; ONTHEFLY is reserved (returns ENOTSUP);
- * AUTO picks STORED. */
+/* How the operators are held. STORED keeps both operators, their transposes
+ * and their row-blocked copies resident in HBM. ONTHEFLY keeps only the
+ * geometry: every apply regenerates the two operators its direction needs
+ * (FP64 geometry, sort, row blocks), applies them and releases them, so an
+ * idle plan holds almost no device memory, at the price of most of a plan
+ * build per apply (a 128^3 forward measured 0.36 ms stored, 52 ms on the
+ * fly). AUTO therefore keeps the operators resident unless they would take
+ * more than half of the device's memory. Results are bitwise the same in
+ * either mode. */
 typedef enum { SRT_OP_AUTO = 0, SRT_OP_STORED = 1, SRT_OP_ONTHEFLY = 2 } srt_opmode;
 
 /* Voxel basis the operators discretise (Sec. 3.1 uses piecewise-constant
@@ -98,6 +104,8 @@ typedef struct {
   int32_t basis;           /* srt_basis of the plan */
   int32_t n_rho;           /* size of the stage-2 radial grid (n_radii unless
                               the plan has a grid of its own) */
+  int32_t mode;            /* SRT_OP_STORED or SRT_OP_ONTHEFLY (AUTO resolved) */
+  int64_t operator_bytes;  /* device bytes of all operators when built */
 } srt_plan_info;
 
 /*
@@ -110,13 +118,12 @@ typedef struct {
  *   radii       host, n_radii sphere radii, > 0 and strictly increasing
  *   value_dtype SRT_F32 or SRT_F64 (type of volumes and data)
  *   weight_dtype SRT_F32/BF16/F16 with F32 values; SRT_F64 with F64 values
- *   mode        SRT_OP_AUTO or SRT_OP_STORED
+ *   mode        SRT_OP_AUTO, SRT_OP_STORED or SRT_OP_ONTHEFLY
  *   device      HIP device ordinal
  *   hip_stream  stream the build runs on (the call returns after the build
  *               has finished)
  *   out         receives the plan; released with srt_plan_destroy
- * Errors: EINVAL (arguments), ENOTSUP (ONTHEFLY, > 2^31 nonzeros), ENOMEM,
- * EDEVICE.
+ * Errors: EINVAL (arguments), ENOTSUP (> 2^31 nonzeros), ENOMEM, EDEVICE.
  */
 srt_status srt_plan_create(const srt_grid *grid, double cyl_radius,
                            const double *angles, int32_t n_angles,
@@ -205,12 +212,14 @@ srt_status srt_plan_create_desc(const srt_plan_desc *desc, void *hip_stream, srt
  *              overlap)
  *   workspace_bytes  size of workspace (ignored when workspace is NULL)
  * vol and data must be aligned to the size of value_dtype.
- * With a caller workspace and stage timing off, the call only launches
- * kernels on hip_stream (no allocation, memset, copy or wait), so it can be
- * captured into a HIP graph and replayed; the plan's own workspace may be
- * allocated on first use and cannot.
+ * With a stored plan, a caller workspace and stage timing off, the call only
+ * launches kernels on hip_stream (no allocation, memset, copy or wait), so it
+ * can be captured into a HIP graph and replayed; the plan's own workspace may
+ * be allocated on first use and cannot. An on-the-fly plan (SRT_OP_ONTHEFLY)
+ * builds its operators in the call and returns after the apply has finished
+ * on hip_stream; calls on one such plan must not overlap.
  * Errors: EINVAL (NULL or misaligned arrays, batch < 1, workspace too small),
- * ENOMEM (own workspace), EDEVICE.
+ * ENOMEM (own workspace, on-the-fly operators), EDEVICE.
  */
 srt_status srt_forward(srt_plan *plan, const void *vol, void *data, int32_t batch,
                        void *workspace, size_t workspace_bytes, void *hip_stream);
@@ -238,9 +247,9 @@ srt_status srt_adjoint(srt_plan *plan, const void *data, void *vol, int32_t batc
  * caller. Nothing in the array has to start at zero; each call overwrites
  * what it reads. Stage timing (srt_plan_set_timing) does not record these
  * calls.
- * Errors: EINVAL (as srt_forward, and when the workspace srt_plan_footprint
- * reports for this batch exceeds 256 MiB), ENOTSUP (device ordinal >= 64),
- * EDEVICE.
+ * Errors: EINVAL (as srt_forward, when the workspace srt_plan_footprint
+ * reports for this batch exceeds 256 MiB, and for an on-the-fly plan),
+ * ENOTSUP (device ordinal >= 64), EDEVICE.
  */
 srt_status srt_forward_noalloc(srt_plan *plan, const void *vol, void *data, int32_t batch,
                                void *hip_stream);

@@ -39,7 +39,8 @@ class SrtPlanInfo(ctypes.Structure):
                 ("live_radii", ctypes.c_int32), ("n_angles", ctypes.c_int32),
                 ("n_z", ctypes.c_int32), ("n_radii", ctypes.c_int32),
                 ("weight_scale_a12", ctypes.c_double), ("weight_scale_a34", ctypes.c_double),
-                ("basis", ctypes.c_int32), ("n_rho", ctypes.c_int32)]
+                ("basis", ctypes.c_int32), ("n_rho", ctypes.c_int32),
+                ("mode", ctypes.c_int32), ("operator_bytes", ctypes.c_int64)]
 
 
 class SrtPlanDesc(ctypes.Structure):

@@ -818,7 +818,16 @@ Status apply(srt_plan *p, const void *in, void *out, int32_t B, void *ws, size_t
     p->timed[adjoint ? 1 : 0].push_back(rec);
     mk.rec = &p->timed[adjoint ? 1 : 0].back();
   }
-  return run(p, in, out, B, P, Q, s, mk, adjoint);
+  if (p->mode != SRT_OP_ONTHEFLY) return run(p, in, out, B, P, Q, s, mk, adjoint);
+  // On the fly: regenerate the two operators this direction applies, apply
+  // them, and release them once the stream has finished with them.
+  SRT_TRY(build_operators(p, s, adjoint ? kAdjointTiles : kForwardTiles));
+  Status st = run(p, in, out, B, P, Q, s, mk, adjoint);
+  const hipError_t e = hipStreamSynchronize(s);
+  release_operators(p);
+  if (!st.ok()) return st;
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  return Status{};
 }
 
 // ---- the allocation-free forward (srt_forward_noalloc)
@@ -851,6 +860,9 @@ Status scratch_address(int dev, void **out) {
 
 Status forward_noalloc(srt_plan *p, const void *vol, void *data, int32_t B, hipStream_t s) {
   SRT_TRY(check_apply(p, vol, data, B));
+  if (p->mode == SRT_OP_ONTHEFLY)
+    return fail(SRT_EINVAL, "srt_forward_noalloc: an on-the-fly plan allocates its operators "
+                            "in every apply");
   const size_t need = workspace_bytes(p, B);
   if (need > kScratchBytes)
     return fail(SRT_EINVAL, "srt_forward_noalloc: this plan and batch need " + std::to_string(need) +

@@ -41,14 +41,7 @@ srt_status finish(const Status &s) { return s.code; }
 
 void destroy_contents(srt_plan *p) {
   clear_timing(p);
-  p->a12.release();
-  p->a12t.release();
-  p->a34.release();
-  p->a34t.release();
-  p->t12.release();
-  p->t12t.release();
-  p->t34.release();
-  p->t34t.release();
+  release_operators(p);
   (void)hipFree(p->d_geom);
   (void)hipFree(p->own_ws);
   p->d_geom = nullptr;
@@ -95,8 +88,8 @@ Status create(const srt_grid *grid, int32_t basis, const double *col_xy, int32_t
   const bool pair_ok = (vdt == SRT_F32 && (wdt == SRT_F32 || wdt == SRT_BF16 || wdt == SRT_F16)) ||
                        (vdt == SRT_F64 && wdt == SRT_F64);
   if (!pair_ok) return fail(SRT_EINVAL, "unsupported (value, weight) dtype pair");
-  if (mode == SRT_OP_ONTHEFLY) return fail(SRT_ENOTSUP, "on-the-fly operators are not built");
-  if (mode != SRT_OP_AUTO && mode != SRT_OP_STORED) return fail(SRT_EINVAL, "unknown mode");
+  if (mode != SRT_OP_AUTO && mode != SRT_OP_STORED && mode != SRT_OP_ONTHEFLY)
+    return fail(SRT_EINVAL, "unknown mode");
   // Index ranges: every dense index below must fit in int32 rows/cols.
   const int64_t npix = (int64_t)grid->ms * grid->ms;
   if (npix > INT32_MAX || (int64_t)na * nl > INT32_MAX || (int64_t)nh * nl > INT32_MAX ||
@@ -154,54 +147,30 @@ Status create(const srt_grid *grid, int32_t basis, const double *col_xy, int32_t
   g.nr = nr;
   g.basis = basis;
 
-  Coo pieces;
-  auto free_pieces = [&]() {
-    (void)hipFree(pieces.keys);
-    (void)hipFree(pieces.vals);
-    pieces = Coo{};
-  };
-  Status st = a12_pieces(g, s, &pieces);
-  if (st.ok()) st = compact_a12(&pieces, nr, npix, s, &p->live);
-  if (st.ok())
-    st = build_csr_pair(&pieces, (int64_t)na * p->live, npix, wdt, s, &p->a12, &p->a12t);
-  free_pieces();
-  if (st.ok()) st = a34_pieces(g, p->live, s, &pieces);
-  if (st.ok())
-    st = build_csr_pair(&pieces, (int64_t)nh * nl, (int64_t)p->live * g.mz, wdt, s, &p->a34,
-                        &p->a34t);
-  free_pieces();
-  // Row-blocked copies for the applies: compact blocks of kRB rows whose
-  // arcs share cells (at kRB = 128: 8 columns x 16 radii, 16 heights x 8
-  // radii, 16 x 8 rho-z cells, 8 x 16 pixels). Rows processed side by side
-  // get equal work per chunk: one radius at 8 columns (A12), one radius at 8
-  // heights (A34), 4 rho-neighbouring cells at one z (A34^T), 4
-  // y-neighbouring pixels (A12^T). Shapes, slot order and block numbering
-  // tiles (2 column groups for A12, 2 height groups for A34, 4 rho groups
-  // for A34^T, plain row-major for A12^T) were measured at 256^3 under the
-  // kernels' work order. The forward operators cut their blocks' columns into
-  // chunks in polar order about the block (sectors of the block's arcs).
-  const int64_t L = p->live;
-  const int me = vdt == SRT_F64 ? kE64 : kE32;
-  const int64_t bh = kRB / 16;  // 16 or 8
-  ColumnOrder o12, o34, plain;
-  o12.kind = 1;
-  o12.cx = g.cx;
-  o12.cy = g.cy;
-  o12.ms = g.ms;
-  o12.x0 = g.x0;
-  o12.dxy = g.dxy;
-  o34.kind = 2;
-  o34.zpos = g.zpos;
-  o34.rho = g.rho;
-  o34.mz = g.mz;
-  o34.z0 = g.z0;
-  o34.dz = g.dz;
-  if (st.ok()) st = build_tiled(p->a12, RowGrid{na, L, 8, kRB / 8, true, 2}, me, o12, s, &p->t12);
-  if (st.ok())
-    st = build_tiled(p->a12t, RowGrid{grid->ms, grid->ms, bh, 16, true, 1}, me, plain, s, &p->t12t);
-  if (st.ok()) st = build_tiled(p->a34, RowGrid{nh, nl, 16, bh, true, 2}, me, o34, s, &p->t34);
-  if (st.ok())
-    st = build_tiled(p->a34t, RowGrid{L, grid->mz, 16, bh, true, 4}, me, plain, s, &p->t34t);
+  Status st = build_operators(p, s, kAllTiles);
+  if (st.ok()) {
+    p->nnz12 = p->a12.nnz;
+    p->nnz34 = p->a34.nnz;
+    p->scale12 = p->a12.scale;
+    p->scale34 = p->a34.scale;
+    p->op_bytes = operator_bytes(p);
+    // AUTO keeps the operators resident unless they would take more than
+    // half of the device's memory: regenerating them in an apply costs most
+    // of a plan build (a 128^3 forward measured 0.36 ms stored, 52 ms on the
+    // fly), so a plan that fits stays stored.
+    srt_opmode m = mode;
+    if (m == SRT_OP_AUTO) {
+      size_t free_b = 0, total_b = 0;
+      m = hipMemGetInfo(&free_b, &total_b) == hipSuccess && p->op_bytes > total_b / 2
+              ? SRT_OP_ONTHEFLY
+              : SRT_OP_STORED;
+    }
+    p->mode = m;
+    if (m == SRT_OP_ONTHEFLY) {
+      SRT_HIP(hipStreamSynchronize(s));
+      release_operators(p);
+    }
+  }
   if (!st.ok()) return bail(st);
   p->magic = kPlanMagic;
   *out = p;
@@ -241,6 +210,80 @@ size_t dtype_size(srt_dtype t) {
     case SRT_F32: return 4;
     default: return 2;
   }
+}
+
+size_t operator_bytes(const srt_plan *p) {
+  return p->a12.bytes() + p->a12t.bytes() + p->a34.bytes() + p->a34t.bytes() + p->t12.bytes() +
+         p->t12t.bytes() + p->t34.bytes() + p->t34t.bytes();
+}
+
+void release_operators(srt_plan *p) {
+  p->a12.release();
+  p->a12t.release();
+  p->a34.release();
+  p->a34t.release();
+  p->t12.release();
+  p->t12t.release();
+  p->t34.release();
+  p->t34t.release();
+}
+
+Status build_operators(srt_plan *p, hipStream_t s, unsigned tiles) {
+  const Geometry &g = p->geo;
+  const int64_t na = g.na, nh = g.nh, nl = g.nl, nr = g.nr;
+  const int64_t npix = (int64_t)g.ms * g.ms;
+  const srt_dtype wdt = p->wdtype;
+  Coo pieces;
+  auto free_pieces = [&]() {
+    (void)hipFree(pieces.keys);
+    (void)hipFree(pieces.vals);
+    pieces = Coo{};
+  };
+  Status st = a12_pieces(g, s, &pieces);
+  if (st.ok()) st = compact_a12(&pieces, (int32_t)nr, npix, s, &p->live);
+  if (st.ok())
+    st = build_csr_pair(&pieces, na * p->live, npix, wdt, s, &p->a12, &p->a12t);
+  free_pieces();
+  if (st.ok()) st = a34_pieces(g, p->live, s, &pieces);
+  if (st.ok())
+    st = build_csr_pair(&pieces, nh * nl, (int64_t)p->live * g.mz, wdt, s, &p->a34, &p->a34t);
+  free_pieces();
+  // Row-blocked copies for the applies: compact blocks of kRB rows whose
+  // arcs share cells (at kRB = 128: 8 columns x 16 radii, 16 heights x 8
+  // radii, 16 x 8 rho-z cells, 8 x 16 pixels). Rows processed side by side
+  // get equal work per chunk: one radius at 8 columns (A12), one radius at 8
+  // heights (A34), 4 rho-neighbouring cells at one z (A34^T), 4
+  // y-neighbouring pixels (A12^T). Shapes, slot order and block numbering
+  // tiles (2 column groups for A12, 2 height groups for A34, 4 rho groups
+  // for A34^T, plain row-major for A12^T) were measured at 256^3 under the
+  // kernels' work order. The forward operators cut their blocks' columns into
+  // chunks in polar order about the block (sectors of the block's arcs).
+  const int64_t L = p->live;
+  const int me = p->vdtype == SRT_F64 ? kE64 : kE32;
+  const int64_t bh = kRB / 16;  // 16 or 8
+  ColumnOrder o12, o34, plain;
+  o12.kind = 1;
+  o12.cx = g.cx;
+  o12.cy = g.cy;
+  o12.ms = g.ms;
+  o12.x0 = g.x0;
+  o12.dxy = g.dxy;
+  o34.kind = 2;
+  o34.zpos = g.zpos;
+  o34.rho = g.rho;
+  o34.mz = g.mz;
+  o34.z0 = g.z0;
+  o34.dz = g.dz;
+  if (st.ok() && (tiles & kTileA12))
+    st = build_tiled(p->a12, RowGrid{na, L, 8, kRB / 8, true, 2}, me, o12, s, &p->t12);
+  if (st.ok() && (tiles & kTileA12t))
+    st = build_tiled(p->a12t, RowGrid{g.ms, g.ms, bh, 16, true, 1}, me, plain, s, &p->t12t);
+  if (st.ok() && (tiles & kTileA34))
+    st = build_tiled(p->a34, RowGrid{nh, nl, 16, bh, true, 2}, me, o34, s, &p->t34);
+  if (st.ok() && (tiles & kTileA34t))
+    st = build_tiled(p->a34t, RowGrid{L, g.mz, 16, bh, true, 4}, me, plain, s, &p->t34t);
+  if (!st.ok()) release_operators(p);
+  return st;
 }
 
 }  // namespace srt
@@ -339,11 +382,12 @@ srt_status srt_plan_footprint(const srt_plan *plan, int32_t batch, size_t *resid
   Status st = validate_plan(plan);
   if (!st.ok()) return finish(st);
   if (batch <= 0) return finish(fail(SRT_EINVAL, "batch must be >= 1"));
-  if (resident)
-    *resident = plan->a12.bytes() + plan->a12t.bytes() + plan->a34.bytes() + plan->a34t.bytes() +
-                plan->t12.bytes() + plan->t12t.bytes() + plan->t34.bytes() + plan->t34t.bytes() +
-                sizeof(double) * (2 * (size_t)plan->geo.na + plan->geo.nh + plan->geo.nl +
-                                  plan->geo.nr);
+  const size_t geom = sizeof(double) * (2 * (size_t)plan->geo.na + plan->geo.nh +
+                                        plan->geo.nl + plan->geo.nr);
+  // an on-the-fly plan holds only its geometry; each apply regenerates its
+  // operators, at most all of op_bytes, beside the workspace
+  const bool otf = plan->mode == SRT_OP_ONTHEFLY;
+  if (resident) *resident = geom + (otf ? 0 : plan->op_bytes);
   if (workspace) *workspace = workspace_bytes(plan, batch);
   return SRT_OK;
 }
@@ -352,16 +396,18 @@ srt_status srt_plan_get_info(const srt_plan *plan, srt_plan_info *info) {
   Status st = validate_plan(plan);
   if (!st.ok()) return finish(st);
   if (!info) return finish(fail(SRT_EINVAL, "info is NULL"));
-  info->nnz_a12 = plan->a12.nnz;
-  info->nnz_a34 = plan->a34.nnz;
+  info->nnz_a12 = plan->nnz12;
+  info->nnz_a34 = plan->nnz34;
   info->live_radii = plan->live;
   info->n_angles = plan->geo.na;
   info->n_z = plan->geo.nh;
   info->n_radii = plan->geo.nl;
-  info->weight_scale_a12 = plan->a12.scale;
-  info->weight_scale_a34 = plan->a34.scale;
+  info->weight_scale_a12 = plan->scale12;
+  info->weight_scale_a34 = plan->scale34;
   info->basis = plan->geo.basis;
   info->n_rho = plan->geo.nr;
+  info->mode = plan->mode;
+  info->operator_bytes = (int64_t)plan->op_bytes;
   return SRT_OK;
 }
 
@@ -369,16 +415,31 @@ srt_status srt_plan_export_coo(const srt_plan *plan, int32_t which, int64_t capa
                                int64_t *nnz, int32_t *rows, int32_t *cols, double *vals) {
   Status st = validate_plan(plan);
   if (!st.ok()) return finish(st);
-  const Csr *m = which == 0 ? &plan->a12 : which == 1 ? &plan->a34 : which == 2 ? &plan->a12t
-                 : which == 3 ? &plan->a34t : nullptr;
-  if (!m) return finish(fail(SRT_EINVAL, "which must be 0..3"));
+  if (which < 0 || which > 3) return finish(fail(SRT_EINVAL, "which must be 0..3"));
   if (!nnz) return finish(fail(SRT_EINVAL, "nnz is NULL"));
-  *nnz = m->nnz;
+  const int64_t n = which == 0 || which == 2 ? plan->nnz12 : plan->nnz34;
+  *nnz = n;
   if (capacity == 0) return SRT_OK;
-  if (capacity < m->nnz) return finish(fail(SRT_EINVAL, "capacity smaller than nnz"));
+  if (capacity < n) return finish(fail(SRT_EINVAL, "capacity smaller than nnz"));
   if (!rows || !cols || !vals) return finish(fail(SRT_EINVAL, "NULL output array"));
   DeviceGuard dg(plan->device);
   if (dg.err != hipSuccess) return finish(hip_fail(dg.err, "hipSetDevice"));
+  // an on-the-fly plan regenerates its CSR operators for the copy (the
+  // plan's observable state does not change)
+  srt_plan *mp = const_cast<srt_plan *>(plan);
+  struct Regen {
+    srt_plan *p = nullptr;
+    ~Regen() {
+      if (p) release_operators(p);
+    }
+  } regen;
+  if (plan->mode == SRT_OP_ONTHEFLY) {
+    regen.p = mp;
+    st = build_operators(mp, nullptr, 0);
+    if (!st.ok()) return finish(st);
+  }
+  const Csr *m = which == 0 ? &plan->a12 : which == 1 ? &plan->a34 : which == 2 ? &plan->a12t
+                                                                               : &plan->a34t;
   std::vector<int32_t> rp((size_t)m->nrows + 1);
   const size_t wsz = dtype_size(m->wdtype);
   std::vector<unsigned char> raw(wsz * (size_t)m->nnz);

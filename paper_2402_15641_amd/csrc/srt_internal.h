@@ -190,6 +190,13 @@ struct srt_plan {
   uint32_t magic = 0;
   int32_t device = 0;
   srt_dtype vdtype = SRT_F32, wdtype = SRT_F32;
+  // SRT_OP_STORED: the operators below stay resident. SRT_OP_ONTHEFLY: they
+  // are empty between applies; each apply regenerates what it needs from the
+  // geometry and releases it again.
+  srt_opmode mode = SRT_OP_STORED;
+  int64_t nnz12 = 0, nnz34 = 0;      // operator sizes, kept for either mode
+  double scale12 = 1.0, scale34 = 1.0;
+  size_t op_bytes = 0;               // bytes of all operators when built
   srt::Geometry geo;
   double *d_geom = nullptr;  // angles | zpos | radii
   int32_t live = 0;          // live rho cells
@@ -203,6 +210,17 @@ struct srt_plan {
 
 namespace srt {
 constexpr uint32_t kPlanMagic = 0x53525431u;  // "SRT1"
+// Row-blocked operators build_operators makes (the CSR pair of each operator
+// is always built): bit per apply direction's needs.
+constexpr unsigned kTileA12 = 1, kTileA12t = 2, kTileA34 = 4, kTileA34t = 8;
+constexpr unsigned kForwardTiles = kTileA12 | kTileA34, kAdjointTiles = kTileA12t | kTileA34t;
+constexpr unsigned kAllTiles = kForwardTiles | kAdjointTiles;
+// Builds the plan's operators from its geometry on stream s (FP64 geometry,
+// CSR pairs, the requested row-blocked copies) and sets `live`; on failure
+// everything built is released.
+Status build_operators(srt_plan *p, hipStream_t s, unsigned tiles);
+void release_operators(srt_plan *p);
+size_t operator_bytes(const srt_plan *p);
 size_t workspace_bytes(const srt_plan *p, int32_t batch);
 // One forward (Alg. 1) or adjoint (Alg. 2) apply of `batch` items on stream s
 // (what srt_forward / srt_adjoint run; arguments validated there as well).

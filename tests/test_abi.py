@@ -63,9 +63,24 @@ def test_invalid_arguments_rejected(over, needle):
     assert needle in msg
 
 
-def test_onthefly_mode_not_supported():
-    st, out, msg = _create(mode=2)
-    assert st == B.SRT_ENOTSUP
+def test_unknown_mode_rejected():
+    st, out, msg = _create(mode=7)
+    assert st == B.SRT_EINVAL and out is None and "mode" in msg
+
+
+def test_info_struct_matches_header():
+    """The binding's srt_plan_info lists the header's fields in the same order."""
+    import os
+    import re
+    hdr = open(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                            "include", "srt.h")).read()
+    body = hdr[hdr.index("int64_t nnz_a12;"):hdr.index("} srt_plan_info;")]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    fields = []
+    for decl in body.split(";"):
+        if decl.strip():
+            fields += [n.strip() for n in decl.split(None, 1)[1].split(",")]
+    assert fields == [f for f, _ in B.SrtPlanInfo._fields_]
 
 
 def test_null_plan_calls():
