@@ -136,15 +136,17 @@ struct RowGrid {
 // narrow sector that every arc of the block crosses with nearly the same
 // length, so rows run side by side with little padding, divergence or
 // barrier wait (CPU emulation at 256^3: useful issue slots 0.48 -> 0.82 for
-// A12, 0.62 -> 0.79 for A34).
+// A12, 0.62 -> 0.79 for A34). The centre used is that of the block's
+// numbering tile (the mean of its tile's sensor columns or heights), so that
+// blocks running side by side walk the same sectors.
 struct ColumnOrder {
   int kind = 0;  // 0: column index; 1: A12 about the block's columns; 2: A34 about its heights
   // kind 1: pixel p = j * ms + i at (x0 + (i + 1/2) dxy, x0 + (j + 1/2) dxy);
-  // row group i1 = sensor column, centred at (cx[i1], cy[i1])
+  // row index i1 = sensor column, at (cx[i1], cy[i1])
   const double *cx = nullptr, *cy = nullptr;
   int32_t ms = 0;
   double x0 = 0, dxy = 0;
-  // kind 2: column m * mz + k at (rho[m], z0 + (k + 1/2) dz); row group i1 =
+  // kind 2: column m * mz + k at (rho[m], z0 + (k + 1/2) dz); row index i1 =
   // sensor height zpos[i1]
   const double *zpos = nullptr, *rho = nullptr;
   int32_t mz = 0;

@@ -94,3 +94,22 @@ def test_auto_keeps_operators_that_fit_and_noalloc_refuses_onthefly():
     assert st == B.SRT_EINVAL and "on-the-fly" in B.srt_last_error()
     auto.close()
     otf.close()
+
+
+@pytest.mark.parametrize("seed", [3, 8, 14])
+def test_widened_operators_onthefly_equal_stored(seed):
+    """Seeded random geometries (columns anywhere, uneven heights and radii,
+    some with a stage-2 radial grid of their own) on the linear basis: an
+    on-the-fly plan's forward and adjoint equal a stored plan's bitwise."""
+    from paper_2402_15641_amd import SRTPlan
+    from srt_inputs import random_aperture
+    ap = random_aperture(seed, scale=2)
+    plans = [SRTPlan.from_geometry(ap, value_dtype="f32", basis="linear", mode=m)
+             for m in ("stored", "onthefly")]
+    rng = np.random.default_rng(seed)
+    F = torch.from_numpy(rng.uniform(-1, 1, ap.vol_shape)).float().cuda()
+    g = torch.from_numpy(rng.standard_normal(ap.data_shape)).float().cuda()
+    assert torch.equal(plans[0].forward(F), plans[1].forward(F))
+    assert torch.equal(plans[0].adjoint(g), plans[1].adjoint(g))
+    for p in plans:
+        p.close()

@@ -382,6 +382,14 @@ def test_pact256_dot_test(weight):
     assert _dot(Y, g.abs(), F, plan.adjoint(g.abs())) <= 1e-6
 
 
+def test_pact256_sampled_adjoint_f16_weights(pact256_oracle):
+    """At 256^3 with F16 weights (the packed entry layout): the adjoint of data
+    on the 96 sampled planes against the FP64 oracle, within 5e-3."""
+    ap, Ft, fwd, dt, adj = pact256_oracle
+    plan = _plan(ap, "f32", "f16")
+    assert rel_l2(_np(plan.adjoint(dt)), adj) <= 5e-3
+
+
 @pytest.mark.parametrize("weight", ["bf16", "f16"])
 def test_pact256_sampled_forward_16bit_weights(weight):
     """At 256^3 with 16-bit weights (the packed entry layout, in the launch
