@@ -125,29 +125,25 @@ template <> struct Quad4<float, float> {
     w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
   }
 };
-// A packed 16-bit unit (one quad step): weights in words x, y (two per
-// word, low half first), local columns in words z, w.
-template <typename WT> __device__ __forceinline__ float half_weight(uint32_t bits16);
-template <> __device__ __forceinline__ float half_weight<uint16_t>(uint32_t b) {  // bfloat16
-  return __uint_as_float(b << 16);
+// A packed 16-bit entry (one 32-bit word): the weight's bits in the high
+// half, the LDS offset of its staged dense row in the low half (shifted by
+// kPackShift). Each costs one instruction to take apart: a mask (or a
+// conversion) for the weight, a mask-and-or for this lane's address.
+template <typename WT> __device__ __forceinline__ float packed_weight(uint32_t word);
+template <> __device__ __forceinline__ float packed_weight<uint16_t>(uint32_t w) {  // bfloat16
+  return __uint_as_float(w & 0xffff0000u);
 }
-template <> __device__ __forceinline__ float half_weight<_Float16>(uint32_t b) {
+template <> __device__ __forceinline__ float packed_weight<_Float16>(uint32_t w) {
   // converted once per step; left to itself the compiler folds the
   // conversion into every FMA (v_fma_mix_f32), which measured slower
-  float f = (float)__builtin_bit_cast(_Float16, (uint16_t)b);
+  float f = (float)__builtin_bit_cast(_Float16, (uint16_t)(w >> 16));
   asm volatile("" : "+v"(f));
   return f;
 }
-template <typename WT>
-__device__ __forceinline__ void unpack_unit(const uint4 u, int c[4], float w[4]) {
-  w[0] = half_weight<WT>(u.x & 0xffffu);
-  w[1] = half_weight<WT>(u.x >> 16);
-  w[2] = half_weight<WT>(u.y & 0xffffu);
-  w[3] = half_weight<WT>(u.y >> 16);
-  c[0] = (int)(u.z & 0xffffu);
-  c[1] = (int)(u.z >> 16);
-  c[2] = (int)(u.w & 0xffffu);
-  c[3] = (int)(u.w >> 16);
+// Byte offset, from the chunk's first staged row, of this lane's first piece
+// of the entry's row (row offsets are multiples of 512 bytes, lane_byte < 256).
+__device__ __forceinline__ uint32_t packed_offset(uint32_t w, uint32_t lane_byte) {
+  return ((w & 0xffffu) << kPackShift) | lane_byte;
 }
 template <> struct Quad4<double, double> {
   static __device__ __forceinline__ void load(const uint32_t *raw, int e, double w[4]) {
@@ -158,19 +154,23 @@ template <> struct Quad4<double, double> {
 };
 
 // One chunk's worth of LDS: staged dense rows (row kC stays zero and is what
-// padding entries point at) and the entries' local columns and weights (as
-// stored; 16-bit weights come packed with their columns, one 16-byte unit per
-// quad step, and need no column array). The quads' entry offsets and first
-// entries travel in registers.
+// padding entries point at) and the entries, in one array per buffer: their
+// local columns, then their weights (as stored); 16-bit weights come packed
+// with their rows' offsets, one word per entry, and need no column part. The
+// column (or packed) part has room for one quad step more than a chunk holds,
+// so the read of the step after a segment's last stays inside the buffer
+// (its values are not used). The quads' entry offsets and first entries
+// travel in registers.
 template <typename T, typename WT> struct ChunkLds {
   using V16 = typename Vec16<T>::type;
   static constexpr bool PACKED = sizeof(WT) == 2;
   static constexpr int E = TileShape<T>::E;
-  static constexpr int CWORDS = PACKED ? 1 : E;
-  static constexpr int WWORDS = PACKED ? E : E * (int)sizeof(WT) / 4;
+  static constexpr int CWORDS = E + kQ;
+  static constexpr int WWORDS = PACKED ? 0 : E * (int)sizeof(WT) / 4;
+  static constexpr int EWORDS = CWORDS + WWORDS;
   V16 *dense;
-  int32_t *col;
-  uint32_t *w;
+  int32_t *col;  // local columns (unpacked layouts)
+  uint32_t *w;   // weights (unpacked layouts: after the columns) or packed words
 };
 
 // One workgroup (one per CU) = one row block x one slice of the dense index.
@@ -215,9 +215,10 @@ __device__ __forceinline__ void tiled_body(const int32_t *__restrict__ blk_rows,
   constexpr int VS = S::VS, NV = S::NV, DW = S::DW, PIECES = S::PIECES;
   constexpr int LPG = S::LPG, GROUPS = S::GROUPS, E = S::E, PPW = S::PAIRS_PER_WAVE;
   __shared__ V16 dense0[(kC + 1) * PIECES], dense1[(kC + 1) * PIECES];
-  __shared__ int32_t col0[L::CWORDS], col1[L::CWORDS];
-  __shared__ uint32_t w0[L::WWORDS], w1[L::WWORDS];
-  const L buf0{dense0, col0, w0}, buf1{dense1, col1, w1};
+  // a step's entries are read with one base address and constant offsets
+  __shared__ __align__(16) uint32_t ent0[L::EWORDS], ent1[L::EWORDS];
+  const L buf0{dense0, reinterpret_cast<int32_t *>(ent0), PACKED ? ent0 : ent0 + L::CWORDS};
+  const L buf1{dense1, reinterpret_cast<int32_t *>(ent1), PACKED ? ent1 : ent1 + L::CWORDS};
 
   // remap < 0: a contiguous range per XCD; 0: hardware order; K > 0: chunks of K
   const int bid = remap < 0 ? xcd_local(blockIdx.x, gridDim.x)
@@ -231,6 +232,7 @@ __device__ __forceinline__ void tiled_body(const int32_t *__restrict__ blk_rows,
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lane = tid & 63, grp = lane / LPG, li = lane % LPG;
+  const uint32_t lane_byte = (uint32_t)li * 16u;  // this lane's first piece of a staged row
 
   V16 acc[kQ][NV];
 #pragma unroll
@@ -291,7 +293,7 @@ __device__ __forceinline__ void tiled_body(const int32_t *__restrict__ blk_rows,
                    b.dense + u * PIECES + (i & 1) * (64 / WPV));
       }
     }
-    // weight words (packed: whole units, four bytes per entry)
+    // weight words (packed: one word per entry)
     const int nw = PACKED ? ne : ne * (int)sizeof(WT) / 4;
     const uint32_t *wsrc = PACKED ? reinterpret_cast<const uint32_t *>(ent_w) + ce0
                                   : reinterpret_cast<const uint32_t *>(ent_w + ce0);
@@ -326,12 +328,11 @@ __device__ __forceinline__ void tiled_body(const int32_t *__restrict__ blk_rows,
   // This lane group's quad: its entry range in chunk c and its first step's
   // entries (columns and weights), read from memory, not from LDS.
   const int q = wave * GROUPS + grp;
-  struct HeadU {  // unpacked layouts: the first step's columns and weights
+  struct HeadU {  // unpacked layouts: the first step's columns
     int e0, e1;
     int4 cn;
-    T wn[kQ];
   };
-  struct HeadP {  // packed layout: the first step's unit
+  struct HeadP {  // packed layout: the first step's words
     int e0, e1;
     uint4 un;
   };
@@ -344,64 +345,69 @@ __device__ __forceinline__ void tiled_body(const int32_t *__restrict__ blk_rows,
   auto load_first = [&](int c, Head &h) {
     // an empty segment reads the chunk's first entries instead (in range)
     const int e = chunk_ent[c] + (h.e0 < h.e1 ? h.e0 : 0);
-    if constexpr (PACKED) {
+    if constexpr (PACKED)
       h.un = *reinterpret_cast<const uint4 *>(reinterpret_cast<const uint32_t *>(ent_w) + e);
-    } else {
+    else
       h.cn = *reinterpret_cast<const int4 *>(ent_col + e);
-      Quad4<T, WT>::load(reinterpret_cast<const uint32_t *>(ent_w), e, h.wn);
-    }
   };
-  // This lane group's quad over one staged chunk.
+  // This lane group's quad over one staged chunk. Per step: this step's
+  // weights (unpacked layouts), its kQ * NV dense pieces, then the next
+  // step's columns or packed words, whose LDS latency overlaps the products.
+  // The column registers are the only values carried from step to step.
+  auto fmas = [&](const V16 (&x)[kQ][NV], const T (&ww)[kQ]) {
+#pragma unroll
+    for (int j = 0; j < kQ; ++j)
+#pragma unroll
+      for (int m = 0; m < NV; ++m) {
+        const T *xs = reinterpret_cast<const T *>(&x[j][m]);
+        T *as = reinterpret_cast<T *>(&acc[j][m]);
+#pragma unroll
+        for (int v = 0; v < VS; ++v) as[v] = fma(ww[j], xs[v], as[v]);
+      }
+  };
   auto consume = [&](const L &b, const Head &h) {
     const int e0 = h.e0, e1 = h.e1;
-    int4 cn;
-    uint4 un;
-    T wn[kQ];
     // Keep the loop's own entry reads where they are written (a step ahead):
     // without this the compiler merges them with these first reads into one
     // read at the top of the loop, which stalls every step on it.
     if constexpr (PACKED) {
-      un = h.un;
+      uint4 un = h.un;
       asm volatile("" : "+v"(un.x), "+v"(un.y), "+v"(un.z), "+v"(un.w));
-    } else {
-      cn = h.cn;
+      const char *rows = reinterpret_cast<const char *>(b.dense);
+      // the loop runs on the entry address alone (one add and one compare a step)
+      for (const uint32_t *pe = b.w + e0, *pend = b.w + e1; pe < pend; pe += kQ) {
+        const uint32_t wd[kQ] = {un.x, un.y, un.z, un.w};
+        T ww[kQ];
+        V16 x[kQ][NV];
 #pragma unroll
-      for (int j = 0; j < kQ; ++j) wn[j] = h.wn[j];
-      asm volatile("" : "+v"(cn.x), "+v"(cn.y), "+v"(cn.z), "+v"(cn.w));
-    }
-    for (int e = e0; e < e1; e += kQ) {
-      int cj[kQ];
-      T ww[kQ];
-      if constexpr (PACKED) {
-        unpack_unit<WT>(un, cj, ww);
-      } else {
-        cj[0] = cn.x; cj[1] = cn.y; cj[2] = cn.z; cj[3] = cn.w;
+        for (int j = 0; j < kQ; ++j) {
+          ww[j] = packed_weight<WT>(wd[j]);
+          const uint32_t off = packed_offset(wd[j], lane_byte);
 #pragma unroll
-        for (int j = 0; j < kQ; ++j) ww[j] = wn[j];
-      }
-      V16 x[kQ][NV];
-#pragma unroll
-      for (int j = 0; j < kQ; ++j)
-#pragma unroll
-        for (int m = 0; m < NV; ++m) x[j][m] = b.dense[cj[j] * PIECES + li + m * LPG];
-      // next step's entries, read while this step's rows are in flight
-      // (clamped: the read after the last step is unused)
-      const int en = min(e + kQ, E - kQ);
-      if constexpr (PACKED) {
-        un = *reinterpret_cast<const uint4 *>(b.w + en);
-      } else {
-        cn = *reinterpret_cast<const int4 *>(b.col + en);
-        Quad4<T, WT>::load(b.w, en, wn);
-      }
-#pragma unroll
-      for (int j = 0; j < kQ; ++j)
-#pragma unroll
-        for (int m = 0; m < NV; ++m) {
-          const T *xs = reinterpret_cast<const T *>(&x[j][m]);
-          T *as = reinterpret_cast<T *>(&acc[j][m]);
-#pragma unroll
-          for (int v = 0; v < VS; ++v) as[v] = fma(ww[j], xs[v], as[v]);
+          for (int m = 0; m < NV; ++m)
+            x[j][m] = *reinterpret_cast<const V16 *>(rows + off + m * LPG * 16);
         }
+        un = *reinterpret_cast<const uint4 *>(pe + kQ);
+        fmas(x, ww);
+      }
+    } else {
+      int4 cn = h.cn;
+      asm volatile("" : "+v"(cn.x), "+v"(cn.y), "+v"(cn.z), "+v"(cn.w));
+      for (const int32_t *pc = b.col + e0, *pend = b.col + e1; pc < pend; pc += kQ) {
+        T ww[kQ];
+        if constexpr (sizeof(WT) == 4)  // the weights sit CWORDS words after their columns
+          Quad4<T, WT>::load(reinterpret_cast<const uint32_t *>(pc + L::CWORDS), 0, ww);
+        else
+          Quad4<T, WT>::load(b.w, (int)(pc - b.col), ww);
+        const int cj[kQ] = {cn.x, cn.y, cn.z, cn.w};
+        V16 x[kQ][NV];
+#pragma unroll
+        for (int j = 0; j < kQ; ++j)
+#pragma unroll
+          for (int m = 0; m < NV; ++m) x[j][m] = b.dense[cj[j] * PIECES + li + m * LPG];
+        cn = *reinterpret_cast<const int4 *>(pc + kQ);
+        fmas(x, ww);
+      }
     }
   };
 

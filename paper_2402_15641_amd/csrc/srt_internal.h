@@ -105,9 +105,18 @@ constexpr int kE64 = 468;
 #endif
 constexpr int kQ = 4;      // rows per quad: a lane group runs a quad in lockstep
 // whole quads per chunk, so that every step's four entries start on a
-// 16-byte boundary in LDS (the clamped read past a segment's end included)
+// 16-byte boundary in LDS (the read one step past a segment's end included)
 static_assert(kE32 % kQ == 0 && kE64 % kQ == 0, "entries per chunk come in whole quads");
 constexpr int kNQ = kRB / kQ;  // quads per block
+// One staged dense row in LDS: 32 pieces of 16 bytes (128 FP32 or 64 FP64
+// values of the row's slice).
+constexpr int kStagedRowBytes = 512;
+// Packed 16-bit entries are one 32-bit word each: the weight's bits in the
+// high half and, in the low half, the LDS byte offset of the entry's staged
+// dense row (local column u at u * kStagedRowBytes) shifted right by
+// kPackShift, so that the offset of the all-zero row kC fits 16 bits.
+constexpr int kPackShift = (kC + 1) * kStagedRowBytes <= 65536 ? 0 : 5;
+static_assert(((kC + 1) * kStagedRowBytes >> kPackShift) <= 65536, "row offsets fit 16 bits");
 constexpr int kNW = SRT_WG_WAVES;  // wavefronts per workgroup
 
 // The operator's rows viewed as an n1 x n2 grid (row = i1 * n2 + i2), cut
@@ -164,8 +173,8 @@ struct Tiled {
   int32_t *ent_col = nullptr;      // [nnz] local column (kC = the all-zero padding column)
   void *ent_w = nullptr;           // [nnz] weights in wdtype (0 for padding)
   // With 16-bit weights the entries are packed instead: ent_col is null and
-  // ent_w holds one 16-byte unit per quad step (entries 4u .. 4u+3): their
-  // four weights (as stored), then their four local columns (16-bit each).
+  // ent_w holds one 32-bit word per entry, its weight (as stored) in the high
+  // half and its staged row's LDS offset (kPackShift) in the low half.
   bool packed = false;
   srt_dtype wdtype = SRT_F32;
   double scale = 1.0;

@@ -29,7 +29,7 @@
 //   chunk_ent[c] .. [c+1]         padded entries of chunk c
 //   qseg[c*(kNQ+1) + q]           first entry of quad q, relative to chunk_ent[c]
 //   ent_col[e], ent_w[e]          local column and weight of entry e (16-bit
-//                                 weights: packed units, see Tiled::packed)
+//                                 weights: one packed word, see Tiled::packed)
 #include <hipcub/hipcub.hpp>
 
 #include "srt_internal.h"
@@ -310,10 +310,15 @@ __global__ void k_pad_fill(int64_t n, int32_t *__restrict__ ent_col) {
   if (i < n) ent_col[i] = kC;
 }
 
-// Packed 16-bit entries: padding units have zero weights and columns kC.
-__global__ void k_pad_fill_packed(int64_t nwords, uint32_t *__restrict__ pack) {
+// Packed 16-bit entries: a staged row's LDS offset in the low half of the word.
+__host__ __device__ constexpr uint32_t packed_row(int u) {
+  return ((uint32_t)u * kStagedRowBytes) >> kPackShift;
+}
+
+// Packed padding entries: weight 0, the all-zero row kC.
+__global__ void k_pad_fill_packed(int64_t n, uint32_t *__restrict__ pack) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < nwords) pack[i] = (i & 2) ? ((uint32_t)kC | ((uint32_t)kC << 16)) : 0u;
+  if (i < n) pack[i] = packed_row(kC);
 }
 
 // Entry i (in (chunk, slot) order) goes to row j = slot % kQ of its quad at
@@ -336,13 +341,13 @@ __global__ void k_scatter(const uint64_t *__restrict__ key2s, const int32_t *__r
   ent_w[dst] = vals[idx_sorted[src]];
 }
 
-// As k_scatter, into the packed 16-bit layout: entry dst is lane j = dst % 4
-// of unit dst / 4 (halfwords 0-3 weights, 4-7 local columns).
+// As k_scatter, into the packed 16-bit layout: entry dst is word dst, the
+// weight's bits in its high half, the local column's staged row in the low.
 __global__ void k_scatter_packed(const uint64_t *__restrict__ key2s, const int32_t *__restrict__ perm2,
                                  int64_t nnz, const int64_t *__restrict__ rawstart,
                                  const int64_t *__restrict__ qstart, const int32_t *__restrict__ local,
                                  const int32_t *__restrict__ idx_sorted,
-                                 const uint16_t *__restrict__ vals, uint16_t *__restrict__ pack) {
+                                 const uint16_t *__restrict__ vals, uint32_t *__restrict__ pack) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nnz) return;
   const int64_t sid = (int64_t)key2s[i];
@@ -351,9 +356,7 @@ __global__ void k_scatter_packed(const uint64_t *__restrict__ key2s, const int32
   const int64_t k = i - rawstart[sid];
   const int64_t dst = qstart[c * kNQ + slot / kQ] + kQ * k + slot % kQ;
   const int32_t src = perm2[i];
-  const int64_t u = dst >> 2, j = dst & 3;
-  pack[u * 8 + j] = vals[idx_sorted[src]];
-  pack[u * 8 + 4 + j] = (uint16_t)local[src];
+  pack[dst] = ((uint32_t)vals[idx_sorted[src]] << 16) | packed_row(local[src]);
 }
 
 int bits_for(uint64_t v) {
@@ -527,8 +530,8 @@ Status build_tiled(const Csr &m, const RowGrid &g, int max_ent, const ColumnOrde
   if (npad >= INT32_MAX) return fail(SRT_ENOTSUP, "too many padded operator entries");
   T.nnz = npad;
   const size_t wsz = dtype_size(m.wdtype);
-  // npad is a multiple of kQ (every quad segment is), so packed entries form
-  // whole 16-byte units
+  // npad is a multiple of kQ (every quad segment is), so a quad step's four
+  // packed words form one 16-byte unit
   T.packed = wsz == 2;
   if (T.packed) {
     if (hipMalloc(&T.ent_w, 4 * (size_t)(npad > 0 ? npad : 4)) != hipSuccess) return oom();
@@ -564,7 +567,7 @@ Status build_tiled(const Csr &m, const RowGrid &g, int max_ent, const ColumnOrde
         hipLaunchKernelGGL(k_scatter_packed, dim3(nblocks(nnz, t)), dim3(t), 0, s,
                            key2s.as<uint64_t>(), perm2.as<int32_t>(), nnz, rawstart.as<int64_t>(),
                            qstart.as<int64_t>(), local.as<int32_t>(), idx_sorted.as<int32_t>(),
-                           (const uint16_t *)m.vals, (uint16_t *)T.ent_w);
+                           (const uint16_t *)m.vals, (uint32_t *)T.ent_w);
     }
   }
   SRT_HIP(hipGetLastError());
