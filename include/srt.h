@@ -246,7 +246,11 @@ srt_status srt_adjoint(srt_plan *plan, const void *data, void *vol, int32_t batc
  * streams, other threads, other plans) race and must be serialised by the
  * caller. Nothing in the array has to start at zero; each call overwrites
  * what it reads. Stage timing (srt_plan_set_timing) does not record these
- * calls.
+ * calls. The first call on a device looks the array's address up
+ * (hipGetSymbolAddress); a caller that captures the call into a HIP graph
+ * makes one call on that device before capturing. The call itself only
+ * launches kernels on hip_stream (no memset, copy or synchronisation), so it
+ * can be captured and replayed.
  * Errors: EINVAL (as srt_forward, when the workspace srt_plan_footprint
  * reports for this batch exceeds 256 MiB, and for an on-the-fly plan),
  * ENOTSUP (device ordinal >= 64), EDEVICE.
