@@ -669,9 +669,12 @@ size_t buffer_elems(const srt_plan *p, int32_t B) {
   return (size_t)B * std::max(v, std::max(gsz, y));
 }
 
+// With `stage2` the data stay in stage 2's layout Yt[h][l][b][a] (angles
+// fastest, items interleaved): the forward leaves out its last layout pass and
+// the adjoint its first. The solvers keep their data-space vectors that way.
 template <typename T, typename WT>
 Status forward_impl(srt_plan *p, const T *vol, T *data, int32_t B, T *P, T *Q, hipStream_t s,
-                    const Marks &mk) {
+                    const Marks &mk, bool stage2) {
   const Geometry &g = p->geo;
   const int L = p->live, M2 = g.ms * g.ms, NR = g.nh * g.nl;
   const int D1 = B * g.mz, D2 = B * g.na;
@@ -694,17 +697,18 @@ Status forward_impl(srt_plan *p, const T *vol, T *data, int32_t B, T *P, T *Q, h
                        s));
   SRT_TRY(mk.at(3));
   // Stage 2 (Alg. 1 second product): Yt[h][l][b][a]
-  SRT_TRY((spmm<T, WT>(Stage::s2_fwd, p->t34, P, Q, D2, s)));
+  SRT_TRY((spmm<T, WT>(Stage::s2_fwd, p->t34, P, stage2 ? data : Q, D2, s)));
   SRT_TRY(mk.at(4));
   // Yt[r][b][a] -> data[b][a][r]
-  SRT_TRY(transpose<T>(Q, data, TDesc{NR, g.na, B, 1, D2, g.na, 0, NR, (int64_t)g.na * NR, 0}, s));
+  if (!stage2)
+    SRT_TRY(transpose<T>(Q, data, TDesc{NR, g.na, B, 1, D2, g.na, 0, NR, (int64_t)g.na * NR, 0}, s));
   SRT_TRY(mk.at(5));
   return Status{};
 }
 
 template <typename T, typename WT>
 Status adjoint_impl(srt_plan *p, const T *data, T *vol, int32_t B, T *P, T *Q, hipStream_t s,
-                    const Marks &mk) {
+                    const Marks &mk, bool stage2) {
   const Geometry &g = p->geo;
   const int L = p->live, M2 = g.ms * g.ms, NR = g.nh * g.nl;
   const int D1 = B * g.mz, D2 = B * g.na;
@@ -715,10 +719,11 @@ Status adjoint_impl(srt_plan *p, const T *data, T *vol, int32_t B, T *P, T *Q, h
     return Status{};
   }
   // data[b][a][r] -> Yt[r][b][a]
-  SRT_TRY(transpose<T>(data, P, TDesc{g.na, NR, B, 1, NR, (int64_t)g.na * NR, 0, D2, g.na, 0}, s));
+  if (!stage2)
+    SRT_TRY(transpose<T>(data, P, TDesc{g.na, NR, B, 1, NR, (int64_t)g.na * NR, 0, D2, g.na, 0}, s));
   SRT_TRY(mk.at(1));
   // Alg. 2 first product: Gt'[l'][k][b][a] = A34^T Yt
-  SRT_TRY((spmm<T, WT>(Stage::s2_adj, p->t34t, P, Q, D2, s)));
+  SRT_TRY((spmm<T, WT>(Stage::s2_adj, p->t34t, stage2 ? data : P, Q, D2, s)));
   SRT_TRY(mk.at(2));
   // Gt'[l'][k][b][a] -> G'[a][l'][b][k]
   SRT_TRY(transpose<T>(Q, P,
@@ -779,30 +784,30 @@ Status check_apply(const srt_plan *p, const void *in, const void *out, int32_t B
 
 // The value/weight type dispatch of one apply over workspace buffers P, Q.
 Status run(srt_plan *p, const void *in, void *out, int32_t B, void *P, void *Q, hipStream_t s,
-           const Marks &mk, bool adjoint) {
+           const Marks &mk, bool adjoint, bool stage2 = false) {
   if (p->vdtype == SRT_F64) {
     using T = double;
-    return adjoint ? adjoint_impl<T, double>(p, (const T *)in, (T *)out, B, (T *)P, (T *)Q, s, mk)
-                   : forward_impl<T, double>(p, (const T *)in, (T *)out, B, (T *)P, (T *)Q, s, mk);
+    return adjoint ? adjoint_impl<T, double>(p, (const T *)in, (T *)out, B, (T *)P, (T *)Q, s, mk, stage2)
+                   : forward_impl<T, double>(p, (const T *)in, (T *)out, B, (T *)P, (T *)Q, s, mk, stage2);
   }
   using T = float;
   switch (p->wdtype) {
     case SRT_BF16:
       return adjoint
-                 ? adjoint_impl<T, uint16_t>(p, (const T *)in, (T *)out, B, (T *)P, (T *)Q, s, mk)
-                 : forward_impl<T, uint16_t>(p, (const T *)in, (T *)out, B, (T *)P, (T *)Q, s, mk);
+                 ? adjoint_impl<T, uint16_t>(p, (const T *)in, (T *)out, B, (T *)P, (T *)Q, s, mk, stage2)
+                 : forward_impl<T, uint16_t>(p, (const T *)in, (T *)out, B, (T *)P, (T *)Q, s, mk, stage2);
     case SRT_F16:
       return adjoint
-                 ? adjoint_impl<T, _Float16>(p, (const T *)in, (T *)out, B, (T *)P, (T *)Q, s, mk)
-                 : forward_impl<T, _Float16>(p, (const T *)in, (T *)out, B, (T *)P, (T *)Q, s, mk);
+                 ? adjoint_impl<T, _Float16>(p, (const T *)in, (T *)out, B, (T *)P, (T *)Q, s, mk, stage2)
+                 : forward_impl<T, _Float16>(p, (const T *)in, (T *)out, B, (T *)P, (T *)Q, s, mk, stage2);
     default:
-      return adjoint ? adjoint_impl<T, float>(p, (const T *)in, (T *)out, B, (T *)P, (T *)Q, s, mk)
-                     : forward_impl<T, float>(p, (const T *)in, (T *)out, B, (T *)P, (T *)Q, s, mk);
+      return adjoint ? adjoint_impl<T, float>(p, (const T *)in, (T *)out, B, (T *)P, (T *)Q, s, mk, stage2)
+                     : forward_impl<T, float>(p, (const T *)in, (T *)out, B, (T *)P, (T *)Q, s, mk, stage2);
   }
 }
 
 Status apply(srt_plan *p, const void *in, void *out, int32_t B, void *ws, size_t ws_bytes,
-             hipStream_t s, bool adjoint) {
+             hipStream_t s, bool adjoint, bool stage2 = false) {
   SRT_TRY(check_apply(p, in, out, B));
   if (ws && reinterpret_cast<uintptr_t>(ws) % 16 != 0)
     return fail(SRT_EINVAL, "workspace must be 16-byte aligned");
@@ -824,11 +829,11 @@ Status apply(srt_plan *p, const void *in, void *out, int32_t B, void *ws, size_t
     p->timed[adjoint ? 1 : 0].push_back(rec);
     mk.rec = &p->timed[adjoint ? 1 : 0].back();
   }
-  if (p->mode != SRT_OP_ONTHEFLY) return run(p, in, out, B, P, Q, s, mk, adjoint);
+  if (p->mode != SRT_OP_ONTHEFLY) return run(p, in, out, B, P, Q, s, mk, adjoint, stage2);
   // On the fly: regenerate the two operators this direction applies, apply
   // them, and release them once the stream has finished with them.
   SRT_TRY(build_operators(p, s, adjoint ? kAdjointTiles : kForwardTiles));
-  Status st = run(p, in, out, B, P, Q, s, mk, adjoint);
+  Status st = run(p, in, out, B, P, Q, s, mk, adjoint, stage2);
   const hipError_t e = hipStreamSynchronize(s);
   release_operators(p);
   if (!st.ok()) return st;
@@ -887,8 +892,19 @@ Status forward_noalloc(srt_plan *p, const void *vol, void *data, int32_t B, hipS
 }  // namespace
 
 Status apply_plan(srt_plan *p, const void *in, void *out, int32_t batch, void *ws,
-                  size_t ws_bytes, hipStream_t s, bool adjoint) {
-  return apply(p, in, out, batch, ws, ws_bytes, s, adjoint);
+                  size_t ws_bytes, hipStream_t s, bool adjoint, bool stage2) {
+  return apply(p, in, out, batch, ws, ws_bytes, s, adjoint, stage2);
+}
+
+Status data_to_stage2(srt_plan *p, const void *data, void *out, int32_t B, hipStream_t s) {
+  SRT_TRY(check_apply(p, data, out, B));
+  DeviceScope ds(p->device);
+  if (ds.err != hipSuccess) return hip_fail(ds.err, "hipSetDevice");
+  const Geometry &g = p->geo;
+  const int NR = g.nh * g.nl, D2 = B * g.na;
+  const TDesc d{g.na, NR, B, 1, NR, (int64_t)g.na * NR, 0, D2, g.na, 0};
+  if (p->vdtype == SRT_F64) return transpose<double>((const double *)data, (double *)out, d, s);
+  return transpose<float>((const float *)data, (float *)out, d, s);
 }
 
 size_t workspace_bytes(const srt_plan *p, int32_t batch) {

@@ -47,30 +47,67 @@ template <typename T> struct V;
 template <> struct V<float> { using t = float4; static constexpr int n = 4; };
 template <> struct V<double> { using t = double2; static constexpr int n = 2; };
 
+// Where element j (0 <= j < n) of batch item b of B sits: the items'
+// vectors are cut into runs of `run` elements and the runs of all items
+// interleaved, run k of item b at (k * B + b) * run. With run == n the items
+// lie one after another (b * n + j); data vectors in stage 2's layout
+// [h][l][b][a] have run == n_angles. A grid-stride walk over j steps the run
+// index and the offset within the run instead of dividing per element.
+struct ItemWalk {
+  int64_t run, B, b, k, o, dk, dO;
+  __device__ ItemWalk(int64_t j0, int64_t stride, int64_t run_, int B_, int b_)
+      : run(run_), B(B_), b(b_), k(j0 / run_), o(j0 % run_), dk(stride / run_), dO(stride % run_) {}
+  __device__ int64_t pos() const { return (k * B + b) * run + o; }
+  __device__ void next() {
+    k += dk;
+    o += dO;
+    if (o >= run) {
+      o -= run;
+      ++k;
+    }
+  }
+};
+
 // part[b * kRedBlocks + blk] = sum over this block's share of item b of x*y,
-// in FP64: each thread sums a fixed stride of the item, then a fixed tree.
+// in FP64: each thread sums a fixed stride of the item's elements (in the
+// item's own order j, whatever the layout), then a fixed tree. In the vector
+// form n and run count 16-byte vectors.
 template <typename T, bool VEC>
 __global__ __launch_bounds__(kRedThreads) void k_dot_partial(const T *__restrict__ x,
                                                              const T *__restrict__ y, int64_t n,
+                                                             int64_t run,
                                                              double *__restrict__ part) {
   __shared__ double red[kRedThreads];
   const int b = blockIdx.y, blk = blockIdx.x, t = threadIdx.x;
-  const T *xb = x + (size_t)b * n, *yb = y + (size_t)b * n;
   const int64_t stride = (int64_t)kRedBlocks * kRedThreads;
+  const int64_t j0 = (int64_t)blk * kRedThreads + t;
   double acc = 0.0;
   if constexpr (VEC) {
     using VT = typename V<T>::t;
     constexpr int W = V<T>::n;
-    const VT *xv = reinterpret_cast<const VT *>(xb), *yv = reinterpret_cast<const VT *>(yb);
-    for (int64_t i = (int64_t)blk * kRedThreads + t; i < n / W; i += stride) {
-      const VT a = xv[i], c = yv[i];
+    const VT *xv = reinterpret_cast<const VT *>(x), *yv = reinterpret_cast<const VT *>(y);
+    auto term = [&](int64_t q) {
+      const VT a = xv[q], c = yv[q];
       const T *as = reinterpret_cast<const T *>(&a), *cs = reinterpret_cast<const T *>(&c);
 #pragma unroll
       for (int k = 0; k < W; ++k) acc += (double)as[k] * (double)cs[k];
+    };
+    if (run == n) {  // items one after another: plain offsets
+      for (int64_t i = j0; i < n / W; i += stride) term((int64_t)b * (n / W) + i);
+    } else {
+      ItemWalk it(j0, stride, run / W, gridDim.y, b);
+      for (int64_t i = j0; i < n / W; i += stride, it.next()) term(it.pos());
     }
   } else {
-    for (int64_t i = (int64_t)blk * kRedThreads + t; i < n; i += stride)
-      acc += (double)xb[i] * (double)yb[i];
+    if (run == n) {
+      for (int64_t i = j0; i < n; i += stride) acc += (double)x[b * n + i] * (double)y[b * n + i];
+    } else {
+      ItemWalk it(j0, stride, run, gridDim.y, b);
+      for (int64_t i = j0; i < n; i += stride, it.next()) {
+        const int64_t q = it.pos();
+        acc += (double)x[q] * (double)y[q];
+      }
+    }
   }
   red[t] = acc;
   __syncthreads();
@@ -95,33 +132,46 @@ __global__ void k_dot_final(const double *__restrict__ part, int batch, double *
 __device__ __forceinline__ double ratio(double num, double den) { return den > 0.0 ? num / den : 0.0; }
 
 // y = a * x + y  (XPAY false)  or  y = x + a * y  (XPAY true), per batch item
-// b with a = sign * num[b] / den[b] (a zero denominator gives a = 0).
+// b with a = sign * num[b] / den[b] (a zero denominator gives a = 0); items
+// laid out in runs as for k_dot_partial.
 template <typename T, bool VEC, bool XPAY>
 __global__ void k_update(T *__restrict__ y, const T *__restrict__ x, const double *__restrict__ num,
-                         const double *__restrict__ den, double sign, int64_t n) {
+                         const double *__restrict__ den, double sign, int64_t n, int64_t run) {
   const int b = blockIdx.y;
   const T a = (T)(sign * ratio(num[b], den[b]));
-  T *yb = y + (size_t)b * n;
-  const T *xb = x + (size_t)b * n;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t j0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   auto op = [&](T xv, T yv) { return XPAY ? fma(a, yv, xv) : fma(a, xv, yv); };
   if constexpr (VEC) {
     using VT = typename V<T>::t;
     constexpr int W = V<T>::n;
-    VT *yv = reinterpret_cast<VT *>(yb);
-    const VT *xv = reinterpret_cast<const VT *>(xb);
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n / W; i += stride) {
-      VT u = yv[i];
-      const VT w = xv[i];
+    VT *yv = reinterpret_cast<VT *>(y);
+    const VT *xv = reinterpret_cast<const VT *>(x);
+    auto one = [&](int64_t q) {
+      VT u = yv[q];
+      const VT w = xv[q];
       T *us = reinterpret_cast<T *>(&u);
       const T *ws = reinterpret_cast<const T *>(&w);
 #pragma unroll
       for (int k = 0; k < W; ++k) us[k] = op(ws[k], us[k]);
-      yv[i] = u;
+      yv[q] = u;
+    };
+    if (run == n) {  // items one after another: plain offsets
+      for (int64_t i = j0; i < n / W; i += stride) one((int64_t)b * (n / W) + i);
+    } else {
+      ItemWalk it(j0, stride, run / W, gridDim.y, b);
+      for (int64_t i = j0; i < n / W; i += stride, it.next()) one(it.pos());
     }
   } else {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
-      yb[i] = op(xb[i], yb[i]);
+    if (run == n) {
+      for (int64_t i = j0; i < n; i += stride) y[b * n + i] = op(x[b * n + i], y[b * n + i]);
+    } else {
+      ItemWalk it(j0, stride, run, gridDim.y, b);
+      for (int64_t i = j0; i < n; i += stride, it.next()) {
+        const int64_t q = it.pos();
+        y[q] = op(x[q], y[q]);
+      }
+    }
   }
 }
 
@@ -173,23 +223,27 @@ Status run(srt_plan *plan, T *f, const T *g, int32_t B, int32_t n_iter, double *
   double *gam = (double *)(w + L.scal), *gam2 = gam + B, *del = gam + 2 * B;
   double *part = (double *)(w + L.part), *hist = (double *)(w + L.hist);
   constexpr int W = V<T>::n;
-  // vector kernels when every item's vector is a whole number of 16-byte
-  // vectors and the caller's arrays are 16-byte aligned (workspace arrays are)
+  // Data-space vectors (r, q) stay in stage 2's layout [h][l][b][a]: items in
+  // runs of n_angles (one run when B == 1). Volume vectors are item by item.
+  const int64_t drun = B > 1 ? geo.na : nd;
+  // vector kernels when every run is a whole number of 16-byte vectors and
+  // the caller's arrays are 16-byte aligned (workspace arrays are)
   const bool fv = nv % W == 0 && (uintptr_t)f % 16 == 0;
-  auto dot = [&](const T *x, const T *y, int64_t n, bool vec, double *out, double *h) -> Status {
+  auto dot = [&](const T *x, const T *y, int64_t n, int64_t run, bool vec, double *out,
+                 double *h) -> Status {
     if (vec)
-      hipLaunchKernelGGL((k_dot_partial<T, true>), dim3(kRedBlocks, B), dim3(kRedThreads), 0, st, x, y, n, part);
+      hipLaunchKernelGGL((k_dot_partial<T, true>), dim3(kRedBlocks, B), dim3(kRedThreads), 0, st, x, y, n, run, part);
     else
-      hipLaunchKernelGGL((k_dot_partial<T, false>), dim3(kRedBlocks, B), dim3(kRedThreads), 0, st, x, y, n, part);
+      hipLaunchKernelGGL((k_dot_partial<T, false>), dim3(kRedBlocks, B), dim3(kRedThreads), 0, st, x, y, n, run, part);
     hipLaunchKernelGGL(k_dot_final, dim3((B + 63) / 64), dim3(64), 0, st, part, B, out, h);
     SRT_HIP(hipGetLastError());
     return Status{};
   };
-  auto update = [&](T *y, const T *x, int64_t n, bool vec, bool xpay, const double *num,
-                    const double *den, double sign) -> Status {
+  auto update = [&](T *y, const T *x, int64_t n, int64_t run, bool vec, bool xpay,
+                    const double *num, const double *den, double sign) -> Status {
     const dim3 grid(grid_for(vec ? n / W : n), B);
     auto go = [&](auto kern) {
-      hipLaunchKernelGGL(kern, grid, dim3(256), 0, st, y, x, num, den, sign, n);
+      hipLaunchKernelGGL(kern, grid, dim3(256), 0, st, y, x, num, den, sign, n, run);
     };
     if (xpay) {
       if (vec) go(k_update<T, true, true>); else go(k_update<T, false, true>);
@@ -199,24 +253,29 @@ Status run(srt_plan *plan, T *f, const T *g, int32_t B, int32_t n_iter, double *
     SRT_HIP(hipGetLastError());
     return Status{};
   };
-  auto fwd = [&](const T *in, T *out) { return apply_plan(plan, in, out, B, ws, L.ws_bytes, st, false); };
-  auto adj = [&](const T *in, T *out) { return apply_plan(plan, in, out, B, ws, L.ws_bytes, st, true); };
-  const bool vv = nv % W == 0, dv = nd % W == 0;  // workspace vectors
+  auto fwd = [&](const T *in, T *out) {
+    return apply_plan(plan, in, out, B, ws, L.ws_bytes, st, false, true);
+  };
+  auto adj = [&](const T *in, T *out) {
+    return apply_plan(plan, in, out, B, ws, L.ws_bytes, st, true, true);
+  };
+  const bool vv = nv % W == 0, dv = nd % W == 0 && drun % W == 0;  // workspace vectors
 
   SRT_TRY(fwd(f, r));
-  hipLaunchKernelGGL(k_rsub<T>, dim3(grid_for(nd * B)), dim3(256), 0, st, r, g, nd * B);
+  SRT_TRY(data_to_stage2(plan, g, q, B, st));  // q is free until the first iteration
+  hipLaunchKernelGGL(k_rsub<T>, dim3(grid_for(nd * B)), dim3(256), 0, st, r, q, nd * B);
   SRT_HIP(hipGetLastError());
   SRT_TRY(adj(r, s));
   SRT_HIP(hipMemcpyAsync(p, s, sizeof(T) * nv * B, hipMemcpyDeviceToDevice, st));
-  SRT_TRY(dot(s, s, nv, vv, gam, hist));
+  SRT_TRY(dot(s, s, nv, nv, vv, gam, hist));
   for (int k = 1; k <= n_iter; ++k) {
     SRT_TRY(fwd(p, q));
-    SRT_TRY(dot(q, q, nd, dv, del, nullptr));
-    SRT_TRY(update(f, p, nv, fv, false, gam, del, 1.0));   // f += alpha p
-    SRT_TRY(update(r, q, nd, dv, false, gam, del, -1.0));  // r -= alpha q
+    SRT_TRY(dot(q, q, nd, drun, dv, del, nullptr));
+    SRT_TRY(update(f, p, nv, nv, fv, false, gam, del, 1.0));     // f += alpha p
+    SRT_TRY(update(r, q, nd, drun, dv, false, gam, del, -1.0));  // r -= alpha q
     SRT_TRY(adj(r, s));
-    SRT_TRY(dot(s, s, nv, vv, gam2, hist + (size_t)k * B));
-    SRT_TRY(update(p, s, nv, vv, true, gam2, gam, 1.0));   // p = s + beta p
+    SRT_TRY(dot(s, s, nv, nv, vv, gam2, hist + (size_t)k * B));
+    SRT_TRY(update(p, s, nv, nv, vv, true, gam2, gam, 1.0));     // p = s + beta p
     std::swap(gam, gam2);
   }
   if (resid) {
@@ -281,7 +340,7 @@ __global__ void k_normalize(T *__restrict__ v, const T *__restrict__ w,
 }
 
 struct NnlsLayout {
-  size_t r, s, y, ws, scal, part, hist, total;  // byte offsets
+  size_t r, g2, s, y, ws, scal, part, hist, total;  // byte offsets
   size_t ws_bytes;
 };
 
@@ -293,6 +352,7 @@ NnlsLayout nnls_layout(const srt_plan *p, int32_t batch, int32_t n_iter) {
   NnlsLayout L{};
   size_t o = 0;
   L.r = o; o += align_up(dat);
+  L.g2 = o; o += align_up(dat);  // the data in stage 2's layout
   L.s = o; o += align_up(vol);
   L.y = o; o += align_up(vol);
   L.ws_bytes = workspace_bytes(p, batch);
@@ -305,12 +365,12 @@ NnlsLayout nnls_layout(const srt_plan *p, int32_t batch, int32_t n_iter) {
 }
 
 template <typename T>
-Status dot_into(const T *x, const T *y, int64_t n, int32_t B, bool vec, double *part, double *out,
-                double *h, hipStream_t st) {
+Status dot_into(const T *x, const T *y, int64_t n, int64_t run, int32_t B, bool vec, double *part,
+                double *out, double *h, hipStream_t st) {
   if (vec)
-    hipLaunchKernelGGL((k_dot_partial<T, true>), dim3(kRedBlocks, B), dim3(kRedThreads), 0, st, x, y, n, part);
+    hipLaunchKernelGGL((k_dot_partial<T, true>), dim3(kRedBlocks, B), dim3(kRedThreads), 0, st, x, y, n, run, part);
   else
-    hipLaunchKernelGGL((k_dot_partial<T, false>), dim3(kRedBlocks, B), dim3(kRedThreads), 0, st, x, y, n, part);
+    hipLaunchKernelGGL((k_dot_partial<T, false>), dim3(kRedBlocks, B), dim3(kRedThreads), 0, st, x, y, n, run, part);
   hipLaunchKernelGGL(k_dot_final, dim3((B + 63) / 64), dim3(64), 0, st, part, B, out, h);
   SRT_HIP(hipGetLastError());
   return Status{};
@@ -321,24 +381,27 @@ Status run_nnls(srt_plan *plan, T *f, const T *g, int32_t B, int32_t n_iter, dou
                 double *resid, char *w, const NnlsLayout &L, hipStream_t st) {
   const Geometry &geo = plan->geo;
   const int64_t nv = (int64_t)geo.mz * geo.ms * geo.ms, nd = (int64_t)geo.na * geo.nh * geo.nl;
-  T *r = (T *)(w + L.r), *s = (T *)(w + L.s), *y = (T *)(w + L.y);
+  T *r = (T *)(w + L.r), *g2 = (T *)(w + L.g2), *s = (T *)(w + L.s), *y = (T *)(w + L.y);
   void *ws = w + L.ws;
   double *part = (double *)(w + L.part), *hist = (double *)(w + L.hist);
   double *scal = (double *)(w + L.scal);
   constexpr int W = V<T>::n;
-  const bool dv = nd % W == 0;
+  // the residual stays in stage 2's layout [h][l][b][a] (runs of n_angles)
+  const int64_t drun = B > 1 ? geo.na : nd;
+  const bool dv = nd % W == 0 && drun % W == 0;
   const bool fv = (nv * B) % W == 0 && (uintptr_t)f % 16 == 0;
   SRT_HIP(hipMemcpyAsync(y, f, sizeof(T) * nv * B, hipMemcpyDeviceToDevice, st));
+  SRT_TRY(data_to_stage2(plan, g, g2, B, st));
   double t = 1.0;
   for (int k = 0; k < n_iter; ++k) {
     const double t_next = (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;
     const double beta = (t - 1.0) / t_next;
     t = t_next;
-    SRT_TRY(apply_plan(plan, y, r, B, ws, L.ws_bytes, st, false));  // r = A y
-    hipLaunchKernelGGL(k_rsub<T>, dim3(grid_for(nd * B)), dim3(256), 0, st, r, g, nd * B);
-    SRT_HIP(hipGetLastError());                                        // r = g - A y
-    SRT_TRY(dot_into<T>(r, r, nd, B, dv, part, scal, hist + (size_t)k * B, st));
-    SRT_TRY(apply_plan(plan, r, s, B, ws, L.ws_bytes, st, true));   // s = A^T (g - A y)
+    SRT_TRY(apply_plan(plan, y, r, B, ws, L.ws_bytes, st, false, true));  // r = A y
+    hipLaunchKernelGGL(k_rsub<T>, dim3(grid_for(nd * B)), dim3(256), 0, st, r, g2, nd * B);
+    SRT_HIP(hipGetLastError());                                              // r = g - A y
+    SRT_TRY(dot_into<T>(r, r, nd, drun, B, dv, part, scal, hist + (size_t)k * B, st));
+    SRT_TRY(apply_plan(plan, r, s, B, ws, L.ws_bytes, st, true, true));   // s = A^T (g - A y)
     const dim3 grid(grid_for(fv ? nv * B / W : nv * B));
     if (fv)
       hipLaunchKernelGGL((k_fista<T, true>), grid, dim3(256), 0, st, f, y, s, (T)step, (T)beta, nv * B);
@@ -368,11 +431,12 @@ Status run_opnorm2(srt_plan *plan, int32_t n_iter, double *norm2, char *w, const
   hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(nv)), dim3(256), 0, st, v, (T)1, nv);
   SRT_HIP(hipGetLastError());
   for (int k = 0; k < n_iter; ++k) {
-    SRT_TRY(apply_plan(plan, v, u, 1, ws, L.ws_bytes, st, false));   // u = A v
-    SRT_TRY(dot_into<T>(u, u, nd, 1, dv, part, sc, nullptr, st));    // ||A v||^2
-    SRT_TRY(dot_into<T>(v, v, nv, 1, vv, part, sc + 1, nullptr, st));  // ||v||^2
-    SRT_TRY(apply_plan(plan, u, wv, 1, ws, L.ws_bytes, st, true));   // w = A^T A v
-    SRT_TRY(dot_into<T>(wv, wv, nv, 1, vv, part, sc + 2, nullptr, st));
+    // u = A v, kept in stage 2's layout (one item: a single run)
+    SRT_TRY(apply_plan(plan, v, u, 1, ws, L.ws_bytes, st, false, true));
+    SRT_TRY(dot_into<T>(u, u, nd, nd, 1, dv, part, sc, nullptr, st));      // ||A v||^2
+    SRT_TRY(dot_into<T>(v, v, nv, nv, 1, vv, part, sc + 1, nullptr, st));  // ||v||^2
+    SRT_TRY(apply_plan(plan, u, wv, 1, ws, L.ws_bytes, st, true, true));  // w = A^T A v
+    SRT_TRY(dot_into<T>(wv, wv, nv, nv, 1, vv, part, sc + 2, nullptr, st));
     hipLaunchKernelGGL(k_normalize<T>, dim3(grid_for(nv)), dim3(256), 0, st, v, wv, sc + 2, nv);
     SRT_HIP(hipGetLastError());
   }

@@ -235,8 +235,15 @@ size_t operator_bytes(const srt_plan *p);
 size_t workspace_bytes(const srt_plan *p, int32_t batch);
 // One forward (Alg. 1) or adjoint (Alg. 2) apply of `batch` items on stream s
 // (what srt_forward / srt_adjoint run; arguments validated there as well).
+// With `stage2` the data side (the forward's output, the adjoint's input) is
+// in stage 2's layout [h][l][b][a] instead of [b][a][h][l]: angles fastest,
+// the batch items interleaved in runs of n_angles.
 Status apply_plan(srt_plan *p, const void *in, void *out, int32_t batch, void *ws,
-                  size_t ws_bytes, hipStream_t s, bool adjoint);
+                  size_t ws_bytes, hipStream_t s, bool adjoint, bool stage2 = false);
+
+// Data [b][a][h][l] laid out as stage 2's [h][l][b][a] (`out` holds as many
+// elements), on stream s.
+Status data_to_stage2(srt_plan *p, const void *data, void *out, int32_t batch, hipStream_t s);
 
 // Makes `dev` the current device for the scope's lifetime.
 struct DeviceScope {
