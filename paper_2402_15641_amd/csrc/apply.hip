@@ -55,6 +55,7 @@ template <typename T> struct TileShape {
   static constexpr int DW = LPG * NV * VS;       // dense values per slice
   static constexpr int PIECES = DW / VS;         // 16-byte pieces per staged dense row
   static_assert(kNW * GROUPS == kNQ, "one quad per lane group");
+  static_assert(GROUPS == kQuadsPerWave, "quad positions follow the builder's placement");
   static_assert(PIECES == 32, "a staged dense row is half a wavefront of 16-byte pieces");
   static constexpr int NT = kNW * 64;            // threads per workgroup
   static constexpr int E = sizeof(T) == 4 ? kE32 : kE64;  // entries per chunk

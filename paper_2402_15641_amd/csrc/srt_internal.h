@@ -108,6 +108,9 @@ constexpr int kQ = 4;      // rows per quad: a lane group runs a quad in lockste
 // 16-byte boundary in LDS (the read one step past a segment's end included)
 static_assert(kE32 % kQ == 0 && kE64 % kQ == 0, "entries per chunk come in whole quads");
 constexpr int kNQ = kRB / kQ;  // quads per block
+// Quads per wavefront in the stage kernels: quad position p runs on lane group
+// p % kQuadsPerWave of wavefront p / kQuadsPerWave.
+constexpr int kQuadsPerWave = 4;
 // One staged dense row in LDS: 32 pieces of 16 bytes (128 FP32 or 64 FP64
 // values of the row's slice).
 constexpr int kStagedRowBytes = 512;

@@ -32,6 +32,8 @@
 //                                 weights: one packed word, see Tiled::packed)
 #include <hipcub/hipcub.hpp>
 
+#include <type_traits>
+
 #include "srt_internal.h"
 
 namespace srt {
@@ -295,6 +297,105 @@ __global__ void k_quad_len(const int64_t *__restrict__ rawstart, int64_t nquad,
   qlen[t] = kQ * m;
 }
 
+// The quads of a block, placed on the stage kernels' wavefronts. A wavefront
+// steps through a chunk as long as its longest quad while the lanes of its
+// shorter quads idle (masked lanes cost almost as much as active ones), so the
+// quads that share a wavefront should have similar lengths chunk by chunk.
+// Local search from the identity placement: swap two quads of different
+// wavefronts whenever that lowers the sum over the block's chunks of each
+// wavefront's longest quad, in a fixed pair order, until a pass makes no swap
+// (at most kPermPasses passes). One wavefront per block; its lanes split the
+// chunks. Blocks of more than kPermMaxChunks chunks keep the identity.
+// perm[b * kNQ + q] = position of quad q (its rows keep their order).
+constexpr int kPermPasses = 8;
+// a quad's steps in a chunk are at most max_ent / kQ
+using QuadSteps = std::conditional_t<(kE32 / kQ < 256), uint8_t, uint16_t>;
+static_assert(kE32 >= kE64 && kE32 / kQ < 65536, "quad steps fit their type");
+constexpr int kPermMaxChunks = 32768 / (kNQ * (int)sizeof(QuadSteps));  // 32 KB of LDS
+__global__ __launch_bounds__(64) void k_quad_place(const int64_t *__restrict__ chunk0,
+                                                   const int64_t *__restrict__ qlen,
+                                                   int32_t *__restrict__ perm) {
+  static_assert(kNQ <= 64, "one lane per quad position");
+  __shared__ QuadSteps steps[kPermMaxChunks * kNQ];  // [chunk][quad]
+  __shared__ int inv[kNQ];                           // position -> quad
+  const int64_t b = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int64_t c0 = chunk0[b], C = chunk0[b + 1] - c0;
+  if (lane < kNQ) inv[lane] = lane;
+  const bool search = C > 1 && C <= kPermMaxChunks;
+  if (search)
+    for (int64_t i = lane; i < C * kNQ; i += 64) steps[i] = (QuadSteps)(qlen[c0 * kNQ + i] / kQ);
+  __syncthreads();
+  for (int pass = 0; search && pass < kPermPasses; ++pass) {
+    bool swapped = false;
+    for (int pa = 0; pa < kNQ; ++pa)
+      for (int pb = pa + 1; pb < kNQ; ++pb) {
+        const int wa = pa / kQuadsPerWave, wb = pb / kQuadsPerWave;
+        if (wa == wb) continue;
+        const int qa = inv[pa], qb = inv[pb];
+        int d = 0;  // change of the two wavefronts' summed longest quads
+        for (int64_t c = lane; c < C; c += 64) {
+          const QuadSteps *sc = steps + c * kNQ;
+          int oa = 0, na = 0, ob = 0, nb = 0;
+#pragma unroll
+          for (int k = 0; k < kQuadsPerWave; ++k) {
+            const int xa = wa * kQuadsPerWave + k, xb = wb * kQuadsPerWave + k;
+            const int va = sc[inv[xa]], vb = sc[inv[xb]];
+            oa = max(oa, va);
+            ob = max(ob, vb);
+            na = max(na, xa == pa ? (int)sc[qb] : va);
+            nb = max(nb, xb == pb ? (int)sc[qa] : vb);
+          }
+          d += na + nb - oa - ob;
+        }
+        for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o);
+        if (d < 0) {  // the same sum on every lane: a uniform decision
+          __syncthreads();
+          if (lane == 0) {
+            inv[pa] = qb;
+            inv[pb] = qa;
+          }
+          __syncthreads();
+          swapped = true;
+        }
+      }
+    if (!swapped) break;
+  }
+  if (lane < kNQ) perm[b * kNQ + inv[lane]] = lane;
+}
+
+// cblk[c] = the block of chunk c.
+__global__ void k_chunk_blk(const int64_t *__restrict__ chunk0, int64_t nblk,
+                            int32_t *__restrict__ cblk) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nblk) return;
+  for (int64_t c = chunk0[b]; c < chunk0[b + 1]; ++c) cblk[c] = (int32_t)b;
+}
+
+// Quad lengths by position: qpos[c * kNQ + perm(q)] = qlen[c * kNQ + q].
+__global__ void k_place_qlen(const int64_t *__restrict__ qlen, const int32_t *__restrict__ cblk,
+                             const int32_t *__restrict__ perm, int64_t nquad,
+                             int64_t *__restrict__ qpos) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t > nquad) return;
+  if (t == nquad) {
+    qpos[t] = 0;
+    return;
+  }
+  const int64_t c = t / kNQ;
+  qpos[c * kNQ + perm[(int64_t)cblk[c] * kNQ + t % kNQ]] = qlen[t];
+}
+
+// Block rows by position: slot q * kQ + j moves to perm(q) * kQ + j.
+__global__ void k_place_rows(const int32_t *__restrict__ rows, const int32_t *__restrict__ perm,
+                             int64_t nblk, int32_t *__restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nblk * kNQ) return;
+  const int64_t b = t / kNQ;
+  const int q = (int)(t % kNQ), p = perm[t];
+  for (int j = 0; j < kQ; ++j) out[b * kRB + p * kQ + j] = rows[b * kRB + q * kQ + j];
+}
+
 __global__ void k_chunk_meta2(const int64_t *__restrict__ qstart, int64_t nchunk,
                               int32_t *__restrict__ chunk_ent, int32_t *__restrict__ qseg) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -326,7 +427,8 @@ __global__ void k_pad_fill_packed(int64_t n, uint32_t *__restrict__ pack) {
 template <typename W>
 __global__ void k_scatter(const uint64_t *__restrict__ key2s, const int32_t *__restrict__ perm2,
                           int64_t nnz, const int64_t *__restrict__ rawstart,
-                          const int64_t *__restrict__ qstart, const int32_t *__restrict__ local,
+                          const int64_t *__restrict__ qstart, const int32_t *__restrict__ cblk,
+                          const int32_t *__restrict__ place, const int32_t *__restrict__ local,
                           const int32_t *__restrict__ idx_sorted, const W *__restrict__ vals,
                           int32_t *__restrict__ ent_col, W *__restrict__ ent_w) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -335,7 +437,8 @@ __global__ void k_scatter(const uint64_t *__restrict__ key2s, const int32_t *__r
   const int64_t c = sid / kRB;
   const int slot = (int)(sid % kRB);
   const int64_t k = i - rawstart[sid];
-  const int64_t dst = qstart[c * kNQ + slot / kQ] + kQ * k + slot % kQ;
+  const int pos = place[(int64_t)cblk[c] * kNQ + slot / kQ];
+  const int64_t dst = qstart[c * kNQ + pos] + kQ * k + slot % kQ;
   const int32_t src = perm2[i];  // position in (block, column) order
   ent_col[dst] = local[src];
   ent_w[dst] = vals[idx_sorted[src]];
@@ -345,7 +448,8 @@ __global__ void k_scatter(const uint64_t *__restrict__ key2s, const int32_t *__r
 // weight's bits in its high half, the local column's staged row in the low.
 __global__ void k_scatter_packed(const uint64_t *__restrict__ key2s, const int32_t *__restrict__ perm2,
                                  int64_t nnz, const int64_t *__restrict__ rawstart,
-                                 const int64_t *__restrict__ qstart, const int32_t *__restrict__ local,
+                                 const int64_t *__restrict__ qstart, const int32_t *__restrict__ cblk,
+                                 const int32_t *__restrict__ place, const int32_t *__restrict__ local,
                                  const int32_t *__restrict__ idx_sorted,
                                  const uint16_t *__restrict__ vals, uint32_t *__restrict__ pack) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -354,7 +458,8 @@ __global__ void k_scatter_packed(const uint64_t *__restrict__ key2s, const int32
   const int64_t c = sid / kRB;
   const int slot = (int)(sid % kRB);
   const int64_t k = i - rawstart[sid];
-  const int64_t dst = qstart[c * kNQ + slot / kQ] + kQ * k + slot % kQ;
+  const int pos = place[(int64_t)cblk[c] * kNQ + slot / kQ];
+  const int64_t dst = qstart[c * kNQ + pos] + kQ * k + slot % kQ;
   const int32_t src = perm2[i];
   pack[dst] = ((uint32_t)vals[idx_sorted[src]] << 16) | packed_row(local[src]);
 }
@@ -523,7 +628,23 @@ Status build_tiled(const Csr &m, const RowGrid &g, int max_ent, const ColumnOrde
                      nseg, rawstart.as<int64_t>());
   hipLaunchKernelGGL(k_quad_len, dim3(nblocks(nquad + 1, t)), dim3(t), 0, s, rawstart.as<int64_t>(),
                      nquad, qlen.as<int64_t>());
-  SRT_TRY(scan_to_i64(qlen.as<int64_t>(), qstart.as<int64_t>(), nquad + 1, s, oom));
+  // 4. quads placed on wavefronts by length (positions), rows and lengths moved with them
+  Buf place, cblk, qpos, rows0;
+  if (place.alloc(4 * (size_t)nblk * kNQ) || cblk.alloc(4 * (size_t)(nchunk > 0 ? nchunk : 1)) ||
+      qpos.alloc(8 * (nquad + 1)) || rows0.alloc(4 * (size_t)nblk * kRB))
+    return oom();
+  if (nblk > 0) {
+    hipLaunchKernelGGL(k_quad_place, dim3((unsigned)nblk), dim3(64), 0, s, chunk0.as<int64_t>(),
+                       qlen.as<int64_t>(), place.as<int32_t>());
+    hipLaunchKernelGGL(k_chunk_blk, dim3(nblocks(nblk, t)), dim3(t), 0, s, chunk0.as<int64_t>(),
+                       nblk, cblk.as<int32_t>());
+    SRT_HIP(hipMemcpyAsync(rows0.p, T.blk_rows, 4 * (size_t)nblk * kRB, hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(k_place_rows, dim3(nblocks(nblk * kNQ, t)), dim3(t), 0, s,
+                       rows0.as<int32_t>(), place.as<int32_t>(), nblk, T.blk_rows);
+  }
+  hipLaunchKernelGGL(k_place_qlen, dim3(nblocks(nquad + 1, t)), dim3(t), 0, s, qlen.as<int64_t>(),
+                     cblk.as<int32_t>(), place.as<int32_t>(), nquad, qpos.as<int64_t>());
+  SRT_TRY(scan_to_i64(qpos.as<int64_t>(), qstart.as<int64_t>(), nquad + 1, s, oom));
   int64_t npad = 0;
   SRT_HIP(hipMemcpyAsync(&npad, qstart.as<int64_t>() + nquad, 8, hipMemcpyDeviceToHost, s));
   SRT_HIP(hipStreamSynchronize(s));
@@ -554,19 +675,22 @@ Status build_tiled(const Csr &m, const RowGrid &g, int max_ent, const ColumnOrde
       case 8:
         hipLaunchKernelGGL(k_scatter<uint64_t>, dim3(nblocks(nnz, t)), dim3(t), 0, s,
                            key2s.as<uint64_t>(), perm2.as<int32_t>(), nnz, rawstart.as<int64_t>(),
-                           qstart.as<int64_t>(), local.as<int32_t>(), idx_sorted.as<int32_t>(),
+                           qstart.as<int64_t>(), cblk.as<int32_t>(), place.as<int32_t>(),
+                           local.as<int32_t>(), idx_sorted.as<int32_t>(),
                            (const uint64_t *)m.vals, T.ent_col, (uint64_t *)T.ent_w);
         break;
       case 4:
         hipLaunchKernelGGL(k_scatter<uint32_t>, dim3(nblocks(nnz, t)), dim3(t), 0, s,
                            key2s.as<uint64_t>(), perm2.as<int32_t>(), nnz, rawstart.as<int64_t>(),
-                           qstart.as<int64_t>(), local.as<int32_t>(), idx_sorted.as<int32_t>(),
+                           qstart.as<int64_t>(), cblk.as<int32_t>(), place.as<int32_t>(),
+                           local.as<int32_t>(), idx_sorted.as<int32_t>(),
                            (const uint32_t *)m.vals, T.ent_col, (uint32_t *)T.ent_w);
         break;
       default:
         hipLaunchKernelGGL(k_scatter_packed, dim3(nblocks(nnz, t)), dim3(t), 0, s,
                            key2s.as<uint64_t>(), perm2.as<int32_t>(), nnz, rawstart.as<int64_t>(),
-                           qstart.as<int64_t>(), local.as<int32_t>(), idx_sorted.as<int32_t>(),
+                           qstart.as<int64_t>(), cblk.as<int32_t>(), place.as<int32_t>(),
+                           local.as<int32_t>(), idx_sorted.as<int32_t>(),
                            (const uint16_t *)m.vals, (uint32_t *)T.ent_w);
     }
   }
