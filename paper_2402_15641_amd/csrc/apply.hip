@@ -107,11 +107,27 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void *base, uin
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes,
                                            0x00020000);
 }
+// The 16-byte buffer copy is written as one asm block rather than through
+// the LDS-copy builtin. For the builtin the compiler cannot tell that the
+// copies into the next chunk's buffer never alias the reads of the current
+// one, and it holds the first step of every chunk until all of this
+// wavefront's copies have landed (vmcnt). Hidden from it, a copy is awaited
+// only where the kernel says so: wait_vmem before the barrier that publishes
+// the buffer. The "memory" clobber keeps memory accesses on their side of the
+// copy. The block sets M0 (the LDS destination, the same for the whole
+// wavefront) for the copy and restores it; the copy has no register outputs.
 __device__ __forceinline__ void buf_dma16(__amdgpu_buffer_rsrc_t r, uint32_t off, void *dst) {
-  __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_void_t *)dst, 16, (int)off, 0, 0, 0);
-}
-__device__ __forceinline__ void buf_dma4(__amdgpu_buffer_rsrc_t r, uint32_t off, void *dst) {
-  __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_void_t *)dst, 4, (int)off, 0, 0, 0);
+  const uint32_t lds = (uint32_t)(uintptr_t)(lds_void_t *)dst;
+  uint32_t saved;
+  asm volatile(
+      "s_mov_b32 %0, m0\n\t"
+      "s_mov_b32 m0, %3\n\t"
+      "s_nop 0\n\t"
+      "buffer_load_dwordx4 %1, %2, 0 offen lds\n\t"
+      "s_mov_b32 m0, %0"
+      : "=&s"(saved)
+      : "v"(off), "s"(r), "s"(lds)
+      : "memory");
 }
 
 // Waits until every vector memory operation of this wavefront (loads and
