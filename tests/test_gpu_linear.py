@@ -141,9 +141,13 @@ def test_linear_adjoint_is_transpose():
     g.manual_seed(3)
     f = torch.randn((2,) + ap.vol_shape, device="cuda", generator=g)
     d = torch.randn((2,) + ap.data_shape, device="cuda", generator=g)
-    Af, Atd = p.forward(f).double(), p.adjoint(d).double()
-    lhs, rhs = float((Af * d.double()).sum()), float((f.double() * Atd).sum())
-    assert abs(lhs - rhs) <= 1e-6 * float(Af.norm()) * float(d.norm())
+    Af = p.forward(f).double()
+    # N(0,1) data, and its absolute value (no cancellation in <Af, d>); the error is
+    # taken relative to |<Af, d>|, inner products in FP64
+    for dd in (d, d.abs()):
+        Atd = p.adjoint(dd).double()
+        lhs, rhs = float((Af * dd.double()).sum()), float((f.double() * Atd).sum())
+        assert abs(lhs - rhs) <= 1e-6 * abs(lhs), (lhs, rhs)
 
 
 def test_linear_cgls_runs_and_decreases():
