@@ -23,6 +23,10 @@ LIB = os.path.join(PKG, "libsrt.so")
 ARCH = "gfx950"
 
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# Per-source flags. The stage kernels use the compiler's iterative ILP
+# scheduler: at 256^3 their summed time came out 1.3% lower on average over
+# 9 interleaved A/B runs a side, with no register spills in any instance.
+FILE_FLAGS = {"apply.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"]}
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall",
           "-Wno-unused-function", "-I", INCLUDE, "-I", CSRC]
 
@@ -40,7 +44,8 @@ def sources():
 
 def _compile(src: str, verbose: bool) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [hipcc(), *COMMON, *DEVICE_FLAGS, "-c", src, "-o", obj]
+    cmd = [hipcc(), *COMMON, *DEVICE_FLAGS, *FILE_FLAGS.get(os.path.basename(src), []), "-c",
+           src, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
