@@ -70,10 +70,9 @@ PEAK_LDS_TBPS = 256 * 256 * 2.4e9 / 1e12
 LDS_BYTES_PER_INST = 64 * 16  # the stage kernels' LDS instructions are ds_read_b128
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stage_kernels_pact256.json")
 # the stage kernels and the operator format they walk (layout, chunk cut)
-# the kernels, the operator format they walk, and the flags they are built with
+# the kernels and the operator format they walk (plus the flags they are built with)
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2402_15641_amd", "csrc", f)
                   for f in ("apply.hip", "srt_internal.h", "tiled.hip", "plan.hip")]
-KERNEL_SOURCES.append(os.path.join(ROOT, "paper_2402_15641_amd", "build.py"))
 
 
 def log(*a):
@@ -81,9 +80,12 @@ def log(*a):
 
 
 def kernel_source_hash() -> str:
+    from paper_2402_15641_amd import build as srt_build
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         h.update(open(f, "rb").read())
+    flags = [srt_build.COMMON, srt_build.DEVICE_FLAGS, sorted(srt_build.FILE_FLAGS.items())]
+    h.update(json.dumps(flags).encode())
     return h.hexdigest()
 
 
