@@ -84,7 +84,8 @@ def kernel_source_hash() -> str:
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         h.update(open(f, "rb").read())
-    flags = [srt_build.COMMON, srt_build.DEVICE_FLAGS, sorted(srt_build.FILE_FLAGS.items())]
+    common = [f for f in srt_build.COMMON if not os.path.isabs(f)]  # not the include paths
+    flags = [common, srt_build.DEVICE_FLAGS, sorted(srt_build.FILE_FLAGS.items())]
     h.update(json.dumps(flags).encode())
     return h.hexdigest()
 
